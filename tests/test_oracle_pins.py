@@ -1,0 +1,380 @@
+"""Pins of the FP64 oracle against facts fixed by the definitions.
+
+Each check is chosen so that a plausible slip in the oracle (a dropped
+term, a swapped alpha/beta or a/b, a wrong flavour map, a wrong replica
+stride, a wrong sign in a gradient) fails at least one of them:
+
+* one-hot tables recover PDF values (closed form),
+* exact integer brute force in Python ints on tiny inputs,
+* linearity (DIS) and homogeneity / polarisation (hadronic),
+* the a<->b, alpha<->beta swap symmetry of Eq. (1),
+* the flattened luminosity form used by Table 3 (a library matmul),
+* Euler's identity and central finite differences for the gradients,
+* library Cholesky / solve for chi2, closed forms for C = I and diagonal C.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_10547_amd import synth
+
+F = 5          # flavours in the tiny cases (the method does not fix 14)
+X = 4
+
+
+def _pairs(mask):
+    a, b = np.nonzero(mask)
+    return list(zip(a.tolist(), b.tolist()))
+
+
+# ---------------------------------------------------------------------------
+# DIS
+# ---------------------------------------------------------------------------
+
+def test_dis_one_hot_recovers_pdf():
+    rng = np.random.default_rng(10)
+    for trial in range(6):
+        mask = np.zeros(F, np.uint8)
+        mask[rng.choice(F, size=3, replace=False)] = 1
+        flav = np.nonzero(mask)[0]
+        N, R = 7, 3
+        pdf = rng.normal(size=(F, X, R)) + 3.0
+        fk = np.zeros((N, 3, X))
+        picks = []
+        for i in range(N):
+            c, al = rng.integers(0, 3), rng.integers(0, X)
+            fk[i, c, al] = 1.0
+            picks.append((flav[c], al))
+        T = oracle.dis(mask, fk, pdf)
+        for i, (a, al) in enumerate(picks):
+            np.testing.assert_array_equal(T[i], pdf[a, al])
+
+
+def test_dis_integer_brute_force_exact():
+    rng = np.random.default_rng(11)
+    t = synth.integer_dis_table(rng, F, X, ndata=6, nactive=3)
+    pdf = synth.integer_pdf(rng, F, X, 4)
+    T = oracle.dis(t.mask, t.fk, pdf)
+    flav = np.nonzero(t.mask)[0]
+    for i in range(6):
+        for r in range(4):
+            s = 0
+            for c, a in enumerate(flav):
+                for al in range(X):
+                    s += int(t.fk[i, c, al]) * int(pdf[a, al, r])
+            assert T[i, r] == s
+
+
+def test_dis_linearity_and_flat_matmul():
+    rng = np.random.default_rng(12)
+    t = synth.draw_dis_table(rng, synth.xgrid_geom(1e-5, 0.9, 30), 40, 9)
+    f = rng.normal(size=(14, 30, 5))
+    g = rng.normal(size=(14, 30, 5))
+    a, b = 1.7, -0.3
+    lhs = oracle.dis(t.mask, t.fk, a * f + b * g)
+    rhs = a * oracle.dis(t.mask, t.fk, f) + b * oracle.dis(t.mask, t.fk, g)
+    assert oracle.normwise_rel(lhs, rhs) < 1e-13
+    flav = np.nonzero(t.mask)[0]
+    ref = t.fk.reshape(40, -1) @ f[flav].reshape(-1, 5)
+    assert oracle.normwise_rel(oracle.dis(t.mask, t.fk, f), ref) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# hadronic, Eq. (1)
+# ---------------------------------------------------------------------------
+
+def _pdf_distinct(rng, R):
+    # all-distinct positive values so that any index slip changes the result
+    return rng.permutation(F * X * R).reshape(F, X, R).astype(np.float64) + 1.0
+
+
+def test_had_one_hot_diagonal_and_off_diagonal():
+    rng = np.random.default_rng(20)
+    R = 2
+    pdf = _pdf_distinct(rng, R)
+    mask = np.zeros((F, F), np.uint8)
+    mask[1, 1] = mask[1, 3] = mask[4, 0] = 1
+    pairs = _pairs(mask)
+    N = 3
+    fk = np.zeros((N, len(pairs), X, X))
+    # datapoint 0: (a=b=1, alpha=beta=2) -> f_1(x_2)^2
+    fk[0, pairs.index((1, 1)), 2, 2] = 1.0
+    # datapoint 1: (a=1, b=3, alpha=0, beta=3) -> f_1(x_0) f_3(x_3)
+    fk[1, pairs.index((1, 3)), 0, 3] = 1.0
+    # datapoint 2: (a=4, b=0, alpha=3, beta=1) -> f_4(x_3) f_0(x_1)
+    fk[2, pairs.index((4, 0)), 3, 1] = 1.0
+    s = oracle.had(mask, fk, pdf)
+    np.testing.assert_array_equal(s[0], pdf[1, 2] ** 2)
+    np.testing.assert_array_equal(s[1], pdf[1, 0] * pdf[3, 3])
+    np.testing.assert_array_equal(s[2], pdf[4, 3] * pdf[0, 1])
+
+
+def test_had_integer_brute_force_exact():
+    rng = np.random.default_rng(21)
+    t = synth.integer_had_table(rng, F, X, ndata=3, npairs=6)
+    pdf = synth.integer_pdf(rng, F, X, 3)
+    s = oracle.had(t.mask, t.fk, pdf)
+    pairs = _pairs(t.mask)
+    for i in range(3):
+        for r in range(3):
+            acc = 0
+            for c, (a, b) in enumerate(pairs):
+                for al, be in itertools.product(range(X), range(X)):
+                    acc += int(t.fk[i, c, al, be]) * int(pdf[a, al, r]) * int(pdf[b, be, r])
+            assert s[i, r] == acc
+
+
+def test_had_homogeneity_swap_symmetry_and_luminosity_form():
+    rng = np.random.default_rng(22)
+    xg = synth.xgrid_geom(1e-7, 1.0, 12)
+    t = synth.draw_general_had_table(rng, xg, 9, npairs=30)
+    f = rng.normal(size=(14, 12, 4))
+    s = oracle.had(t.mask, t.fk, f)
+    # homogeneity of degree two
+    assert oracle.normwise_rel(oracle.had(t.mask, t.fk, -2.5 * f), 6.25 * s) < 1e-13
+    # swapping a<->b together with alpha<->beta leaves Eq. (1) unchanged
+    pairs = _pairs(t.mask)
+    mT = np.ascontiguousarray(t.mask.T)
+    pairsT = _pairs(mT)
+    fkT = np.zeros_like(t.fk)
+    for c, (a, b) in enumerate(pairs):
+        fkT[:, pairsT.index((b, a))] = np.transpose(t.fk[:, c], (0, 2, 1))
+    assert oracle.normwise_rel(oracle.had(mT, fkT, f), s) < 1e-13
+    # Table 3 contracts a flattened FK [N x K] with a luminosity [K x R]
+    # built from f (x) f over the active pairs
+    lum = np.stack([f[a][:, None, :] * f[b][None, :, :] for a, b in pairs])  # [np][X][X][R]
+    ref = t.fk.reshape(9, -1) @ lum.reshape(-1, 4)
+    assert oracle.normwise_rel(s, ref) < 1e-12
+
+
+def test_had_bilinear_polarisation():
+    rng = np.random.default_rng(23)
+    xg = synth.xgrid_geom(1e-7, 1.0, 10)
+    t = synth.draw_general_had_table(rng, xg, 5, npairs=20)
+    f = rng.normal(size=(14, 10, 3))
+    g = rng.normal(size=(14, 10, 3))
+    lhs = oracle.had(t.mask, t.fk, f + g)
+    rhs = (oracle.had(t.mask, t.fk, f) + oracle.had(t.mask, t.fk, g)
+           + oracle.had_bilinear(t.mask, t.fk, f, g) + oracle.had_bilinear(t.mask, t.fk, g, f))
+    assert oracle.normwise_rel(lhs, rhs) < 1e-12
+    # symmetric FK: the bilinear form is symmetric in its two PDFs
+    ts = synth.draw_had_table(rng, xg, 4, ndiag=2, noff=5)
+    assert oracle.normwise_rel(oracle.had_bilinear(ts.mask, ts.fk, f, g),
+                               oracle.had_bilinear(ts.mask, ts.fk, g, f)) < 1e-12
+
+
+def test_generated_symmetric_table_is_symmetric():
+    rng = np.random.default_rng(24)
+    t = synth.draw_had_table(rng, synth.xgrid_geom(1e-7, 1.0, 8), 3, ndiag=3, noff=6)
+    pairs = _pairs(t.mask)
+    assert len(pairs) == 3 + 12
+    for c, (a, b) in enumerate(pairs):
+        np.testing.assert_array_equal(t.fk[:, c], np.transpose(t.fk[:, pairs.index((b, a))], (0, 2, 1)))
+
+
+# ---------------------------------------------------------------------------
+# gradients
+# ---------------------------------------------------------------------------
+
+def test_dis_grad_closed_form_euler_and_fd():
+    rng = np.random.default_rng(30)
+    t = synth.draw_dis_table(rng, synth.xgrid_geom(1e-5, 0.9, 6), 8, 3, nflav=F)
+    R = 3
+    f = rng.normal(size=(F, 6, R))
+    gbar = rng.normal(size=(8, R))
+    g = oracle.dis_grad(t.mask, t.fk, gbar)
+    # Euler (degree 1): sum_p f_p g_p = gbar . T, per replica
+    T = oracle.dis(t.mask, t.fk, f)
+    np.testing.assert_allclose(np.einsum("axr,axr->r", f, g), np.sum(gbar * T, axis=0), rtol=1e-12)
+    # inactive flavours get zero
+    assert np.all(g[t.mask == 0] == 0)
+    # central differences are exact for a linear map
+    h = 1e-3
+    for (a, al, r) in [(a, al, r) for a in range(F) for al in range(6) for r in range(R)][::5]:
+        fp = f.copy(); fp[a, al, r] += h
+        fm = f.copy(); fm[a, al, r] -= h
+        fd = (np.sum(gbar * oracle.dis(t.mask, t.fk, fp)) - np.sum(gbar * oracle.dis(t.mask, t.fk, fm))) / (2 * h)
+        assert abs(fd - g[a, al, r]) <= 1e-9 * (1 + abs(g[a, al, r]))
+
+
+def test_had_grad_one_hot_closed_form():
+    rng = np.random.default_rng(31)
+    pdf = _pdf_distinct(rng, 2)
+    mask = np.zeros((F, F), np.uint8)
+    mask[2, 4] = 1
+    fk = np.zeros((1, 1, X, X))
+    fk[0, 0, 1, 3] = 1.0               # sigma = f_2(x_1) f_4(x_3)
+    gbar = np.array([[2.0, -3.0]])
+    g = oracle.had_grad(mask, fk, pdf, gbar)
+    exp = np.zeros_like(g)
+    exp[2, 1] = gbar[0] * pdf[4, 3]
+    exp[4, 3] = gbar[0] * pdf[2, 1]
+    np.testing.assert_array_equal(g, exp)
+
+
+def test_had_grad_euler_and_central_differences():
+    rng = np.random.default_rng(32)
+    xg = synth.xgrid_geom(1e-7, 1.0, 6)
+    t = synth.draw_general_had_table(rng, xg, 5, npairs=9)
+    R = 2
+    f = rng.normal(size=(14, 6, R))
+    gbar = rng.normal(size=(5, R))
+    g = oracle.had_grad(t.mask, t.fk, f, gbar)
+    s = oracle.had(t.mask, t.fk, f)
+    # Euler (degree 2): sum_p f_p g_p = 2 gbar . sigma
+    np.testing.assert_allclose(np.einsum("axr,axr->r", f, g), 2 * np.sum(gbar * s, axis=0), rtol=1e-11)
+    # central differences are exact (up to rounding) for a quadratic
+    h = 1e-2
+    coords = [(a, al, r) for a in range(14) for al in range(6) for r in range(R)]
+    for k in rng.choice(len(coords), size=60, replace=False):
+        a, al, r = coords[k]
+        fp = f.copy(); fp[a, al, r] += h
+        fm = f.copy(); fm[a, al, r] -= h
+        fd = (np.sum(gbar * oracle.had(t.mask, t.fk, fp)) - np.sum(gbar * oracle.had(t.mask, t.fk, fm))) / (2 * h)
+        assert abs(fd - g[a, al, r]) <= 1e-9 * (1 + np.max(np.abs(g)))
+
+
+def test_had_grad_symmetric_fk_is_twice_h():
+    # for symmetric FK both terms of the gradient coincide: g = 2 sum_i gbar_i FK_i f
+    rng = np.random.default_rng(33)
+    xg = synth.xgrid_geom(1e-7, 1.0, 5)
+    t = synth.draw_had_table(rng, xg, 4, ndiag=2, noff=3, nflav=F)
+    f = rng.normal(size=(F, 5, 2))
+    gbar = rng.normal(size=(4, 2))
+    g = oracle.had_grad(t.mask, t.fk, f, gbar)
+    pairs = _pairs(t.mask)
+    H = np.zeros((4, F, 5, 2))
+    for c, (a, b) in enumerate(pairs):
+        H[:, a] += np.einsum("ixy,yr->ixr", t.fk[:, c], f[b])
+    ref = 2 * np.einsum("ir,iaxr->axr", gbar, H)
+    assert oracle.normwise_rel(g, ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# chi2
+# ---------------------------------------------------------------------------
+
+def _spd(rng, n):
+    A = rng.normal(size=(n, n))
+    return A @ A.T + n * np.eye(n)
+
+
+def test_cholesky_matches_library_and_reconstructs():
+    rng = np.random.default_rng(40)
+    for n in (1, 2, 7, 40):
+        C = _spd(rng, n)
+        L = oracle.cholesky(C)
+        np.testing.assert_allclose(L, np.linalg.cholesky(C), rtol=1e-12, atol=1e-12)
+        assert np.linalg.norm(L @ L.T - C) / np.linalg.norm(C) < 1e-13
+        assert np.all(np.triu(L, 1) == 0)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cholesky(-np.eye(3))
+
+
+def test_chi2_identity_zero_diag_and_solve():
+    rng = np.random.default_rng(41)
+    sizes = [3, 5, 1]
+    Ntot, R = sum(sizes), 4
+    sig = rng.normal(size=(Ntot, R))
+    D = rng.normal(size=Ntot)
+    # C = I: chi2 = ||sigma - D||^2, gradient 2 (sigma - D)
+    c, d = oracle.chi2([np.eye(n) for n in sizes], sig, D)
+    np.testing.assert_allclose(c, np.sum((sig - D[:, None]) ** 2, axis=0), rtol=1e-13)
+    np.testing.assert_allclose(d, 2 * (sig - D[:, None]), rtol=1e-13)
+    # D = sigma: zero
+    c0, d0 = oracle.chi2([np.eye(n) for n in sizes], sig, sig[:, 0])
+    assert c0[0] == 0 and np.all(d0[:, 0] == 0)
+    # diagonal C: sum e^2 / c_ii
+    diag = rng.uniform(0.5, 2.0, size=Ntot)
+    Ls, off = [], 0
+    for n in sizes:
+        Ls.append(np.diag(np.sqrt(diag[off:off + n]))); off += n
+    c, _ = oracle.chi2(Ls, sig, D)
+    np.testing.assert_allclose(c, np.sum((sig - D[:, None]) ** 2 / diag[:, None], axis=0), rtol=1e-13)
+    # general block-diagonal C against numpy.linalg.solve
+    Cs = [_spd(rng, n) for n in sizes]
+    c, d = oracle.chi2([oracle.cholesky(C) for C in Cs], sig, D)
+    e = sig - D[:, None]
+    off, ref, dref = 0, np.zeros(R), np.zeros((Ntot, R))
+    for C in Cs:
+        n = C.shape[0]
+        w = np.linalg.solve(C, e[off:off + n])
+        ref += np.sum(e[off:off + n] * w, axis=0)
+        dref[off:off + n] = 2 * w
+        off += n
+    np.testing.assert_allclose(c, ref, rtol=1e-12)
+    np.testing.assert_allclose(d, dref, rtol=1e-11, atol=1e-12)
+
+
+def test_chi2_pseudo_data_statistics():
+    # chi2 of the central prediction against pseudo-data drawn from C has
+    # mean N (the number of points); 200 draws, 5 sigma band
+    rng = np.random.default_rng(42)
+    n = 30
+    central = rng.normal(size=n) * 3.0
+    vals = []
+    for k in range(200):
+        C, D = synth.covariance_block(central, np.random.default_rng([42, k]))
+        c, _ = oracle.chi2([oracle.cholesky(C)], central[:, None], D, want_grad=False)
+        vals.append(c[0])
+    m = np.mean(vals)
+    assert abs(m - n) < 5 * np.sqrt(2 * n / 200)
+
+
+# ---------------------------------------------------------------------------
+# quantisers and the stored-operand mode
+# ---------------------------------------------------------------------------
+
+def test_bf16_matches_torch_on_fp32_inputs():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(50)
+    x = np.concatenate([rng.normal(size=4000) * 10.0 ** rng.integers(-30, 30, size=4000),
+                        np.array([0.0, -0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 2 ** -130, 3.3e38])])
+    x = x.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(oracle.quantize(x, "bf16"), ref)
+
+
+def test_e4m3_matches_torch_in_range_and_saturates():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(51)
+    x = rng.uniform(-440, 440, size=4000) * 10.0 ** rng.integers(-4, 1, size=4000)
+    x = np.concatenate([x, [0.0, 1.0625, 1.1875, 2 ** -10, 3 * 2 ** -11, 2 ** -9, 448.0]])
+    x = x.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(oracle.quantize(x, "e4m3"), ref)
+    np.testing.assert_array_equal(oracle.quantize(np.array([460.0, -1e6, 449.0]), "e4m3"),
+                                  [448.0, -448.0, 448.0])
+
+
+def test_datapoint_scale_is_tight_power_of_two():
+    vals = np.array([0.0, 1e-30, 0.3, 1.0, 1.0000001, 447.9, 448.0, 448.1, 1e5])
+    for fmt, qmax in (("bf16", 1.0), ("e4m3", 448.0)):
+        s = oracle.datapoint_scale(vals, fmt)
+        for v, si in zip(vals, s):
+            m, e = np.frexp(si)
+            assert m == 0.5
+            if v > 0:
+                assert v / si <= qmax and v / (si / 2) > qmax
+
+
+def test_stored_operand_mode_exact_cases():
+    rng = np.random.default_rng(52)
+    # in FP64 the stored forms reproduce the definitions (general FK, mask)
+    xg = synth.xgrid_geom(1e-7, 1.0, 6)
+    t = synth.draw_general_had_table(rng, xg, 4, npairs=25)
+    f = (rng.normal(size=(14, 6, 3)) ** 2).astype(np.float32).astype(np.float64)
+    assert oracle.normwise_rel(oracle.had_quantized(t.mask, t.fk, f, "f64"), oracle.had(t.mask, t.fk, f)) < 1e-13
+    gbar = rng.normal(size=(4, 3)).astype(np.float32).astype(np.float64)
+    assert oracle.normwise_rel(oracle.had_grad_quantized(t.mask, t.fk, f, gbar, "f64"),
+                               oracle.had_grad(t.mask, t.fk, f, gbar)) < 1e-12
+    d = synth.draw_dis_table(rng, xg, 7, 9)
+    assert oracle.normwise_rel(oracle.dis_quantized(d.mask, d.fk, f, "f64"), oracle.dis(d.mask, d.fk, f)) < 1e-13
+    # integer inputs are exact in bf16, so the quantised result is exact
+    ti = synth.integer_had_table(rng, F, X, 3, 7)
+    fi = synth.integer_pdf(rng, F, X, 2)
+    np.testing.assert_array_equal(oracle.had_quantized(ti.mask, ti.fk, fi, "bf16"), oracle.had(ti.mask, ti.fk, fi))
+    di = synth.integer_dis_table(rng, F, X, 5, 3)
+    np.testing.assert_array_equal(oracle.dis_quantized(di.mask, di.fk, fi, "bf16"), oracle.dis(di.mask, di.fk, fi))
