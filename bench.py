@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Throughput of the hadronic FK-table convolution on one MI355X.
+
+Workload: the hadronic global-fit shape (10 datasets, N ~ U{20..1000}, 60
+active ordered flavour pairs from a symmetric mask, x-grid of 50 points,
+R = 100 PDF replicas), seeded synthetic tables and PDFs.  One step is one
+convolution of all datasets (Eq. (1) of the paper, one group launch) with
+the tables stored in BF16; the same step with FP32 tables is timed beside
+it.  Tables and PDFs are resident in HBM before the timed region.
+
+The JSON line carries the headline metric (datapoint*replicas/s, BF16), the
+FP32 figure, per-step latency percentiles, errors, the roofline of the
+dominant kernel (timed with HIP events on its launch stream by the library's
+timing hook), the FP64 CPU oracle's throughput on a bounded sample, and the
+timings of the other steps of the path (DIS convolution, adjoints, FP64
+chi2, a full fit step).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "hadronic FK-conv datapoint·replicas/s bf16 vs fp32 @rel≤5e-3; p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2516.6
+COUNTERS = os.path.join(ROOT, "profiles", "had_fwd_bf16_cfg2_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_10547_amd", "csrc", "conv_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_counters():
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source; else None."""
+    try:
+        d = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in ev])
+    return wall / steps * 1e3, per
+
+
+def kernel_times(c, fn, steps, torch, fkconv):
+    fkconv.fk_timing_read(c.ctx)
+    fkconv.fk_timing_enable(c.ctx, True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    fkconv.fk_timing_enable(c.ctx, False)
+    return fkconv.fk_timing_read(c.ctx)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="shrink dataset sizes (quick checks only; the metric uses 1.0)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip DIS/adjoint/chi2 rows")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the workload shards by dataset, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1909_10547_amd  # noqa: F401
+    from paper_1909_10547_amd import fkconv, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_start = time.perf_counter()
+    w = synth.config2(args.scale)
+    R = w.nrep
+    log(f"generating hadronic tables: ndata={w.ndata}")
+    tabs = []
+    for d in range(len(w.ndata)):
+        tabs.append(w.table(d))
+    log(f"  generated in {time.perf_counter() - t_start:.1f}s")
+    pdf64 = w.pdf(R).astype(np.float32).astype(np.float64)
+    c = fkconv.Context(0)
+    t0 = time.perf_counter()
+    hb = [c.load(t, "bf16") for t in tabs]
+    hf = [c.load(t, "f32") for t in tabs]
+    gb = fkconv.fk_group_create(c.ctx, hb)
+    gf = fkconv.fk_group_create(c.ctx, hf)
+    log(f"  packed and loaded bf16 + fp32 in {time.perf_counter() - t0:.1f}s")
+    Ntot = sum(t.ndata for t in tabs)
+    npairs = [int(t.mask.sum()) for t in tabs]
+    X = tabs[0].fk.shape[-1]
+    elems = sum(t.ndata * p * X * X for t, p in zip(tabs, npairs))
+    x = torch.from_numpy(pdf64.astype(np.float32)).cuda()
+    out_b = torch.empty((Ntot, R), dtype=torch.float32, device="cuda")
+    out_f = torch.empty_like(out_b)
+
+    def step_b():
+        fkconv.fk_conv_had(c.ctx, gb, x, out=out_b)
+
+    def step_f():
+        fkconv.fk_conv_had(c.ctx, gf, x, out=out_f)
+
+    log("timing bf16 / fp32 steps")
+    ms_b, per_b = time_steps(step_b, args.steps, args.warmup, torch)
+    ms_f, per_f = time_steps(step_f, args.steps, args.warmup, torch)
+    kt_b = kernel_times(c, step_b, args.steps, torch, fkconv)
+    kt_f = kernel_times(c, step_f, args.steps, torch, fkconv)
+    value_b = Ntot * R / (ms_b * 1e-3)
+    value_f = Ntot * R / (ms_f * 1e-3)
+    yb = out_b.double().cpu().numpy()
+    yf = out_f.double().cpu().numpy()
+
+    def normwise(y, r):
+        num = np.sqrt(((y - r) ** 2).sum(axis=0))
+        den = np.sqrt((r ** 2).sum(axis=0))
+        return float(np.max(num / den))
+
+    err_b_vs_f = normwise(yb, yf)
+    had_ms, had_n = kt_b["had_fwd"]
+    kern_ms = had_ms / max(had_n, 1)
+    bytes_alg = elems * 2 + pdf64.size * 4 + Ntot * R * 4
+    flops_alg = 2.0 * elems * R
+    achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
+    traffic = traffic_from_counters()
+    hadf_ms, hadf_n = kt_f["had_fwd"]
+    kern_f_ms = hadf_ms / max(hadf_n, 1)
+    result = {
+        "metric": METRIC,
+        "value": value_b,
+        "unit": "datapoint*replicas/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_b,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic: seeded FK tables and PDF replicas with the shapes of the hadronic global-fit workload",
+        "config": {
+            "workload": f"hadronic FK convolution, Eq. (1): {len(tabs)} datasets, {Ntot} datapoints, "
+                        f"{npairs[0]} active flavour pairs, x-grid {X}, R={R} replicas",
+            "datasets": len(tabs), "ndata": Ntot, "nrep": R, "nx": X,
+            "active_pairs": npairs, "fk_elements": elems, "scale": args.scale,
+            "parallelism": "single GPU",
+        },
+        "latency_ms": {"p50": float(np.percentile(per_b, 50)), "p99": float(np.percentile(per_b, 99)),
+                       "fp32_p50": float(np.percentile(per_f, 50)), "fp32_p99": float(np.percentile(per_f, 99))},
+        "fp32": {"value": value_f, "ms_per_step": ms_f, "kernel_ms": kern_f_ms,
+                 "tflops": flops_alg / (kern_f_ms * 1e-3) / 1e12},
+        "speedup_bf16_over_fp32": value_b / value_f,
+        "error": {"bf16_vs_fp32_normwise": err_b_vs_f,
+                  "note": "fp32 is within 1e-5 of the FP64 oracle (tests); FP64 errors on the CPU sample below"},
+        "roofline": {
+            "kernel": "had_fwd_kernel<bf16>",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_alg,
+            "kernel_ms": kern_ms,
+            "mfma_tflops": flops_alg / (kern_ms * 1e-3) / 1e12,
+            "mfma_frac": flops_alg / (kern_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+        },
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt_b.items() if v[1]},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (FP64 oracle on a sample)")
+        # calibrate on two datapoints, then take an evenly spread sample
+        t0 = time.perf_counter()
+        oracle.had(tabs[0].mask, tabs[0].fk[:2], pdf64)
+        per_dp = (time.perf_counter() - t0) / 2
+        k = max(1, int(args.cpu_seconds / per_dp / len(tabs)))
+        rows, refs, gotb, gotf, nsamp = [], [], [], [], 0
+        off = 0
+        t0 = time.perf_counter()
+        for t in tabs:
+            sel = np.unique(np.linspace(0, t.ndata - 1, min(k, t.ndata)).astype(int))
+            refs.append(oracle.had(t.mask, t.fk[sel], pdf64))
+            gotb.append(yb[off + sel])
+            gotf.append(yf[off + sel])
+            nsamp += len(sel)
+            off += t.ndata
+        el = time.perf_counter() - t0
+        ref = np.concatenate(refs)
+        result["cpu_baseline"] = {
+            "value": nsamp * R / el, "unit": "datapoint*replicas/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{nsamp} of {Ntot} datapoints (evenly spaced in every dataset) x {R} replicas, FP64, {el:.1f}s",
+        }
+        result["error"].update({
+            "bf16_vs_fp64_sample_normwise": normwise(np.concatenate(gotb), ref),
+            "fp32_vs_fp64_sample_normwise": normwise(np.concatenate(gotf), ref),
+        })
+        try:
+            result["cpu_baseline"]["cpu_model"] = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                                                   if l.startswith("model name")][0]
+        except (OSError, IndexError):
+            pass
+
+    if not args.no_extras:
+        log("extra rows: DIS, adjoints, chi2, fit step")
+        result["rows"] = extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth)
+
+    fkconv.fk_unload_table(c.ctx, gb)
+    fkconv.fk_unload_table(c.ctx, gf)
+    c.close()
+    result["wall_s"] = time.perf_counter() - t_start
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
+    rows = {}
+    # DIS global-like workload (20 datasets, R=100)
+    w1 = synth.config1(args.scale)
+    dtabs = [w1.table(d) for d in range(len(w1.ndata))]
+    Nd = sum(t.ndata for t in dtabs)
+    x1 = torch.from_numpy(w1.pdf(R).astype(np.float32)).cuda()
+    dis_centrals = []
+    for fmt in ("bf16", "f32"):
+        hs = [c.load(t, fmt) for t in dtabs]
+        g = fkconv.fk_group_create(c.ctx, hs)
+        out = torch.empty((Nd, R), dtype=torch.float32, device="cuda")
+        ms, per = time_steps(lambda: fkconv.fk_conv_dis(c.ctx, g, x1, out=out), args.steps, args.warmup, torch)
+        kt = kernel_times(c, lambda: fkconv.fk_conv_dis(c.ctx, g, x1, out=out), args.steps, torch, fkconv)
+        gout = torch.ones((Nd, R), dtype=torch.float32, device="cuda")
+        msb, _ = time_steps(lambda: fkconv.fk_conv_backward(c.ctx, g, None, gout), args.steps, args.warmup, torch)
+        rows[f"dis_{fmt}"] = {"ndata": Nd, "ms_per_step": ms, "p50_ms": float(np.median(per)),
+                              "kernel_ms": kt["dis_fwd"][0] / max(kt["dis_fwd"][1], 1),
+                              "value": Nd * R / (ms * 1e-3), "adjoint_ms": msb}
+        if fmt == "f32":
+            cen = fkconv.fk_conv_dis(c.ctx, g, x1[:, :, :1].contiguous())[:, 0].double().cpu().numpy()
+            off = 0
+            for t in dtabs:
+                dis_centrals.append(cen[off:off + t.ndata])
+                off += t.ndata
+        fkconv.fk_unload_table(c.ctx, g)
+        for h in hs:
+            fkconv.fk_unload_table(c.ctx, h)
+    # hadronic adjoint
+    Ntot = out_b.shape[0]
+    gbar = torch.ones((Ntot, R), dtype=torch.float32, device="cuda")
+    for fmt, g in (("bf16", gb), ("f32", gf)):
+        ms, _ = time_steps(lambda: fkconv.fk_conv_backward(c.ctx, g, x, gbar), args.steps, args.warmup, torch)
+        kt = kernel_times(c, lambda: fkconv.fk_conv_backward(c.ctx, g, x, gbar), args.steps, torch, fkconv)
+        rows[f"had_adjoint_{fmt}"] = {"ms_per_step": ms,
+                                      "kernel_ms": kt["had_adj"][0] / max(kt["had_adj"][1], 1)}
+    # FP64 chi2 over the datasets of both workloads (block-diagonal covariance)
+    had_c = fkconv.fk_conv_had(c.ctx, gf, x[:, :, :1].contiguous())
+    blocks, centrals, off = [], [], 0
+    for t in tabs:
+        centrals.append(had_c[off:off + t.ndata, 0].double().cpu().numpy())
+        off += t.ndata
+    fit = synth.config3(args.scale)
+    Cs, Ds = fit.covariances(dis_centrals + centrals)
+    cv = fkconv.fk_load_covariance(c.ctx, Cs)
+    D = torch.from_numpy(np.concatenate(Ds)).cuda()
+    Nall = sum(C.shape[0] for C in Cs)
+    sig = torch.randn((Nall, R), dtype=torch.float32, device="cuda")
+    ms, _ = time_steps(lambda: fkconv.fk_chi2(c.ctx, cv, sig, D), args.steps, args.warmup, torch)
+    rows["chi2_fp64"] = {"ndata": Nall, "blocks": len(Cs), "ms_per_step": ms}
+    # full fit step: DIS + hadronic forward (bf16), chi2, both adjoints
+    hs = [c.load(t, "bf16") for t in dtabs]
+    gd = fkconv.fk_group_create(c.ctx, hs)
+    x1c = x  # both workloads share the x-grid [1e-7, 1] of 50 points
+    sig_all = torch.empty((Nall, R), dtype=torch.float32, device="cuda")
+    gpdf = torch.empty_like(x)
+
+    def fit_step():
+        Nd = sum(t.ndata for t in dtabs)
+        fkconv.fk_conv_dis(c.ctx, gd, x1c, out=sig_all[:Nd])
+        fkconv.fk_conv_had(c.ctx, gb, x1c, out=sig_all[Nd:])
+        _, dchi = fkconv.fk_chi2(c.ctx, cv, sig_all, D)
+        fkconv.fk_conv_backward(c.ctx, gd, None, dchi[:Nd].contiguous(), grad_pdf=gpdf)
+        fkconv.fk_conv_backward(c.ctx, gb, x1c, dchi[Nd:].contiguous(), grad_pdf=gpdf, accumulate=True)
+
+    ms, per = time_steps(fit_step, args.steps, args.warmup, torch)
+    rows["fit_step_bf16"] = {"ms_per_step": ms, "p50_ms": float(np.median(per)),
+                             "note": "DIS + hadronic forward, FP64 chi2 with gradient, both adjoints"}
+    fkconv.fk_unload_table(c.ctx, gd)
+    for h in hs:
+        fkconv.fk_unload_table(c.ctx, h)
+    fkconv.fk_unload_covariance(c.ctx, cv)
+    return rows
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,141 @@
+// Internal declarations of the fkconv library: device descriptors shared by
+// the host runtime and the kernels, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fkconv.h"
+
+namespace fk {
+
+// ---------------------------------------------------------------------------
+// Tiling constants
+//
+// Every kernel is a 16-row x (16*NT)-column MFMA tile computed by one wave64.
+// The FK operand is stored in 16-byte "units"; one unit holds E consecutive
+// contraction elements of one row (E = 4 float, 8 bfloat16, 16 e4m3).  A
+// k-step is 4 units per row: lane (g = lane/16, row = lane%16) supplies unit
+// 4t+g of row ``row``; the B operand (PDF, or the adjoint weights) lives in
+// LDS in the same unit layout [unit][column].
+// ---------------------------------------------------------------------------
+constexpr int kWaves = 4;                  // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRpMax = 128;                // replica columns per pass
+constexpr int kUnitsMax = 32;              // units per row and group (LDS B <= 64 KiB)
+constexpr int kTMax = kUnitsMax / 4;       // k-steps per tile
+constexpr int kMaxSeg = 40;                // segments per group descriptor
+constexpr int kMaxNx = 128;                // grid points supported
+constexpr int kDisChunkUnits = kUnitsMax;  // datapoint units per DIS adjoint chunk
+constexpr int kItemUnits = 96;             // forward work per item (units per row)
+
+inline int elems_per_unit(int dtype) {
+  return dtype == FK_F32 ? 4 : (dtype == FK_BF16 ? 8 : 16);
+}
+inline int elem_bytes(int dtype) { return dtype == FK_F32 ? 4 : (dtype == FK_BF16 ? 2 : 1); }
+
+// B-operand descriptor: the contraction index k of a group is the
+// concatenation of ``nseg`` segments; segment s covers source rows
+// seg_row[s] .. seg_row[s]+seg_len[s]-1.  Source 0 is the PDF (row =
+// flavour*nx + x index), source 1 the adjoint weights gbar[i]*s_i (row =
+// datapoint index in the concatenated output).
+struct GroupDesc {
+  int32_t a;        // row flavour of a hadronic group, -1 otherwise
+  int32_t src;      // 0: PDF, 1: adjoint weights
+  int32_t nseg;
+  int32_t K;        // contraction length (sum of seg_len)
+  int32_t KE;       // units per row = ceil(K / E)
+  int32_t pad;
+  int64_t bop_off;  // offset of the staged B operand, in 16-byte units
+  int32_t seg_row[kMaxSeg];
+  int32_t seg_len[kMaxSeg];
+};
+
+// One (table, group) of a plan: where the group's packed FK starts.
+struct SegRef {
+  const uint4 *base;
+  int32_t gdesc;
+  int32_t KE;
+};
+
+// Forward work item.  Hadronic: one 16-datapoint block, groups
+// [seg0, seg1) of one table, waves split the x index alpha.  DIS: up to
+// kWaves consecutive blocks (one per wave), groups [seg0, seg1).
+struct FwdItem {
+  int32_t seg0, seg1;
+  int32_t block0;   // first block of the item within the table
+  int32_t nblk;     // DIS: blocks in the item (<= kWaves); hadronic: 1
+  int32_t ndata;    // datapoints of the table
+  int32_t slot0;    // first partial slot (16 x RP floats each)
+};
+
+// Hadronic adjoint item: one group, blocks [block0, block1) of its table.
+struct HadAdjItem {
+  int32_t seg;
+  int32_t block0, block1;
+  int32_t ndata;
+  int32_t wrow0;    // row of the table's datapoint 0 in the concatenated output
+  int32_t slot;     // partial slot (nx x RP floats)
+};
+
+// DIS adjoint item on the transposed table: rows (flavour, x) in 16-row
+// tiles, contraction over one chunk of datapoints.
+struct DisAdjItem {
+  const uint4 *base;  // packed transposed FK of the chunk, tile 0
+  int32_t gdesc;      // B operand (weights of the chunk's datapoints)
+  int32_t KE;
+  int32_t nrows;      // nact * nx
+  int32_t tile0;      // first 16-row tile of the item
+  int32_t ntile;      // tiles in the item (<= kWaves)
+  int32_t slot0;      // first partial slot (16 x RP floats each)
+};
+
+// Forward reduction of one output block of 16 datapoints.
+struct RedBlock {
+  int32_t orow;     // first output row
+  int32_t nv;       // rows in the block
+  int32_t k0, k1;   // range in the slot index list
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (conv_kernels.hip)
+// ---------------------------------------------------------------------------
+struct ConvLaunch {
+  int dtype;
+  int nt;           // column tiles of 16 (RP = 16*nt)
+  int ncols, c0, R; // columns of this pass, their offset, caller's row stride
+  hipStream_t stream;
+};
+
+hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
+                          const float *gout, const float *scale_all, uint4 *bop);
+hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
+                          const GroupDesc *gd, const uint4 *bop, const float *pdf, int nx,
+                          int lds_units, float *part);
+hipError_t launch_dis_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
+                          const GroupDesc *gd, const uint4 *bop, int lds_units, float *part);
+hipError_t launch_fwd_reduce(const ConvLaunch &L, const RedBlock *blocks, int nblocks,
+                             const int32_t *slot_idx, const float *part, const float *scale_all,
+                             float factor, float *out);
+hipError_t launch_had_adj(const ConvLaunch &L, const HadAdjItem *items, int nitems,
+                          const SegRef *segs, const GroupDesc *gd, const uint4 *bop,
+                          const float *gout, const float *scale_all, int nx, int lds_units,
+                          float *apart);
+hipError_t launch_dis_adj(const ConvLaunch &L, const DisAdjItem *items, int nitems,
+                          const GroupDesc *gd, const uint4 *bop, int lds_units, float *apart);
+hipError_t launch_adj_reduce(const ConvLaunch &L, int nrows_out, const int32_t *row_ptr,
+                             const int64_t *entry_off, const float *apart, int accumulate,
+                             float *g);
+
+// chi2 (chi2_kernels.hip)
+hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off, double *d_a,
+                           double *d_linv, int32_t *d_flag, int maxn, hipStream_t s);
+hipError_t launch_chi2(int nblocks, int nrt, const int32_t *d_rt_block, const int32_t *d_rt_row,
+                       const int32_t *d_n, const int64_t *d_off, const int32_t *d_roff,
+                       const double *d_linv, const float *sigma, const double *data, int R,
+                       int c0, int ncols, double *d_y, double *d_part, double *chi2,
+                       float *dchi2, hipStream_t s);
+
+}  // namespace fk

@@ -1,0 +1,842 @@
+// Host runtime of the fkconv library: context, device-memory budget, table
+// registry, launch plans and the non-serving C entry points.
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+using namespace fk;
+
+namespace {
+thread_local std::string g_create_err;
+
+#define FK_TRY_HIP(c, expr)                                                            \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return set_err(c, FK_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct Guard {
+  std::unique_lock<std::mutex> lk;
+  explicit Guard(fk_ctx *c) : lk(c->mu) {}
+};
+
+}  // namespace
+
+namespace fk {
+
+fk_status set_err(fk_ctx *c, fk_status code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_create_err = buf;
+  return code;
+}
+
+fk_status dev_alloc(fk_ctx *c, size_t bytes, void **p,
+                    std::vector<std::pair<void *, size_t>> *track) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  uint64_t cur = c->used.load();
+  for (;;) {
+    if (cur + bytes > c->budget)
+      return set_err(c, FK_E_BUDGET, "device-memory budget exhausted: %llu used + %llu requested > %llu",
+                     (unsigned long long)cur, (unsigned long long)bytes,
+                     (unsigned long long)c->budget);
+    if (c->used.compare_exchange_weak(cur, cur + bytes)) break;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    c->used -= bytes;
+    *p = nullptr;
+    return set_err(c, FK_E_HIP, "hipMalloc(%llu): %s", (unsigned long long)bytes,
+                   hipGetErrorString(e));
+  }
+  if (track) track->push_back({*p, bytes});
+  return FK_OK;
+}
+
+void dev_free_all(fk_ctx *c, std::vector<std::pair<void *, size_t>> &track) {
+  for (auto &a : track) {
+    if (a.first) (void)hipFree(a.first);
+    c->used -= a.second;
+  }
+  track.clear();
+}
+
+Plan *find_plan(fk_ctx *c, int64_t h) {
+  auto it = c->plans.find(h);
+  return it == c->plans.end() ? nullptr : it->second.get();
+}
+Table *find_table(fk_ctx *c, int64_t h) {
+  auto it = c->tables.find(h);
+  return it == c->tables.end() ? nullptr : it->second.get();
+}
+
+int pick_nt(int ncols) {
+  const int t = (ncols + 15) / 16;
+  if (t <= 1) return 1;
+  if (t == 2) return 2;
+  if (t <= 4) return 4;
+  if (t <= 7) return 7;
+  return 8;
+}
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+template <typename T>
+static fk_status upload(fk_ctx *c, Plan &p, const std::vector<T> &v, T **dst) {
+  void *d = nullptr;
+  fk_status st = dev_alloc(c, std::max<size_t>(v.size(), 1) * sizeof(T), &d, &p.allocs);
+  if (st) return st;
+  if (!v.empty()) FK_TRY_HIP(c, hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = (T *)d;
+  return FK_OK;
+}
+
+static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) {
+  const bool had = p.kind == FK_HAD;
+  const int X = p.X, F = p.F;
+  std::vector<GroupDesc> gd;
+  std::vector<SegRef> segs;
+  std::vector<std::vector<int>> segidx(ts.size());
+  size_t bop = 0;
+  auto add_gd = [&](int a, int src, const std::vector<int> &rows, const std::vector<int> &lens,
+                    int K, int KE) {
+    GroupDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.a = a;
+    d.src = src;
+    d.nseg = (int)rows.size();
+    d.K = K;
+    d.KE = KE;
+    d.bop_off = (int64_t)bop;
+    for (size_t s = 0; s < rows.size(); ++s) {
+      d.seg_row[s] = rows[s];
+      d.seg_len[s] = lens[s];
+    }
+    bop += (size_t)((KE + 3) / 4) * 4 * kRpMax;
+    gd.push_back(d);
+    return (int)gd.size() - 1;
+  };
+  p.row0.clear();
+  int row = 0;
+  p.table_bytes = 0;
+  for (auto *t : ts) {
+    p.row0.push_back(row);
+    row += t->N;
+    p.table_bytes += t->fk_bytes + t->fkT_bytes;
+  }
+  p.Ntot = row;
+  std::vector<float> scale_all;
+  for (auto *t : ts) scale_all.insert(scale_all.end(), t->scale.begin(), t->scale.end());
+  p.maxT_fwd = p.maxT_adj = 1;
+  for (size_t t = 0; t < ts.size(); ++t)
+    for (auto &g : ts[t]->groups) {
+      const int gi = add_gd(g.a, 0, g.seg_row, g.seg_len, g.K, g.KE);
+      segs.push_back({(const uint4 *)((const char *)ts[t]->d_fk + g.base * 16), gi, g.KE});
+      segidx[t].push_back((int)segs.size() - 1);
+      p.maxT_fwd = std::max(p.maxT_fwd, (g.KE + 3) / 4);
+    }
+  p.ngd_fwd = (int)gd.size();
+  std::vector<std::vector<int>> chunkgd(ts.size());
+  if (!had)
+    for (size_t t = 0; t < ts.size(); ++t)
+      for (auto &ch : ts[t]->tchunks) {
+        chunkgd[t].push_back(add_gd(-1, 1, {p.row0[t] + ch.i0}, {ch.n}, ch.n, ch.KE));
+        p.maxT_adj = std::max(p.maxT_adj, (ch.KE + 3) / 4);
+      }
+  else
+    p.maxT_adj = p.maxT_fwd;
+  p.ngd_adj = (int)gd.size() - p.ngd_fwd;
+
+  // ---- forward items.  An item runs consecutive groups of one block (DIS:
+  // of up to kWaves blocks) until about kItemUnits units per row are done.
+  // The split depends on the table alone, so a table's result is bitwise
+  // the same alone and inside any group.
+  std::vector<FwdItem> items;
+  std::vector<RedBlock> rblocks;
+  std::vector<int32_t> slot_idx;
+  const double target = kItemUnits;
+  int nslots = 0;
+  for (size_t t = 0; t < ts.size(); ++t) {
+    const Table *T = ts[t];
+    const int nblk = (T->N + 15) / 16;
+    const int nG = (int)T->groups.size();
+    std::vector<std::vector<int>> bslots(nblk);
+    const int step = had ? 1 : kWaves;
+    for (int b0 = 0; b0 < nblk; b0 += step) {
+      const int nb = std::min(step, nblk - b0);
+      int g = 0;
+      while (g < nG) {
+        const int g0 = g;
+        double acc = 0;
+        do {
+          acc += (double)T->groups[g].KE * nb;
+          ++g;
+        } while (g < nG && acc + (double)T->groups[g].KE * nb <= target);
+        FwdItem it;
+        it.seg0 = segidx[t][g0];
+        it.seg1 = segidx[t][g - 1] + 1;
+        it.block0 = b0;
+        it.nblk = nb;
+        it.ndata = T->N;
+        it.slot0 = nslots;
+        for (int w = 0; w < nb; ++w) bslots[b0 + w].push_back(nslots + w);
+        nslots += nb;
+        items.push_back(it);
+      }
+    }
+    for (int bl = 0; bl < nblk; ++bl) {
+      RedBlock rb;
+      rb.orow = p.row0[t] + 16 * bl;
+      rb.nv = std::min(16, T->N - 16 * bl);
+      rb.k0 = (int)slot_idx.size();
+      slot_idx.insert(slot_idx.end(), bslots[bl].begin(), bslots[bl].end());
+      rb.k1 = (int)slot_idx.size();
+      rblocks.push_back(rb);
+    }
+  }
+
+  // ---- adjoint items and the CSR of partial rows per output row (a, x)
+  std::vector<std::vector<int64_t>> rows_out((size_t)F * X);
+  std::vector<HadAdjItem> hadj;
+  std::vector<DisAdjItem> dadj;
+  size_t apart_floats = 0;
+  if (had) {
+    double pairs = 0;
+    for (auto *t : ts) pairs += (double)t->groups.size() * ((t->N + 15) / 16);
+    const int tb = std::max(1, (int)std::lround(pairs / 768.0));
+    int slot = 0;
+    for (size_t t = 0; t < ts.size(); ++t) {
+      const Table *T = ts[t];
+      const int nblk = (T->N + 15) / 16;
+      for (size_t gi = 0; gi < T->groups.size(); ++gi)
+        for (int b0 = 0; b0 < nblk; b0 += tb) {
+          HadAdjItem it;
+          it.seg = segidx[t][gi];
+          it.block0 = b0;
+          it.block1 = std::min(nblk, b0 + tb);
+          it.ndata = T->N;
+          it.wrow0 = p.row0[t];
+          it.slot = slot;
+          const int a = T->groups[gi].a;
+          for (int al = 0; al < X; ++al)
+            rows_out[(size_t)a * X + al].push_back((int64_t)slot * X * kRpMax + (int64_t)al * kRpMax);
+          ++slot;
+          hadj.push_back(it);
+        }
+    }
+    apart_floats = (size_t)slot * X * kRpMax;
+  } else {
+    int slot = 0;
+    for (size_t t = 0; t < ts.size(); ++t) {
+      const Table *T = ts[t];
+      const int nrows = T->nact * X;
+      const int ntile = (nrows + 15) / 16;
+      for (size_t ch = 0; ch < T->tchunks.size(); ++ch) {
+        const TChunk &tc = T->tchunks[ch];
+        for (int q = 0; q < ntile; q += kWaves) {
+          DisAdjItem it;
+          it.base = (const uint4 *)((const char *)T->d_fkT + tc.base * 16);
+          it.gdesc = chunkgd[t][ch];
+          it.KE = tc.KE;
+          it.nrows = nrows;
+          it.tile0 = q;
+          it.ntile = std::min(kWaves, ntile - q);
+          it.slot0 = slot;
+          for (int w = 0; w < it.ntile; ++w)
+            for (int r = 0; r < 16; ++r) {
+              const int lr = 16 * (q + w) + r;
+              if (lr >= nrows) break;
+              const int fl = T->active[lr / X], al = lr % X;
+              rows_out[(size_t)fl * X + al].push_back((int64_t)(slot + w) * 16 * kRpMax +
+                                                       (int64_t)r * kRpMax);
+            }
+          slot += it.ntile;
+          dadj.push_back(it);
+        }
+      }
+    }
+    apart_floats = (size_t)slot * 16 * kRpMax;
+  }
+  std::vector<int32_t> row_ptr(1, 0);
+  std::vector<int64_t> entries;
+  for (auto &r : rows_out) {
+    entries.insert(entries.end(), r.begin(), r.end());
+    row_ptr.push_back((int32_t)entries.size());
+  }
+
+  fk_status st;
+  if ((st = upload(c, p, gd, &p.d_gd))) return st;
+  if ((st = upload(c, p, segs, &p.d_seg))) return st;
+  if ((st = upload(c, p, items, &p.d_fitems))) return st;
+  if ((st = upload(c, p, rblocks, &p.d_rblocks))) return st;
+  if ((st = upload(c, p, slot_idx, &p.d_slot_idx))) return st;
+  if ((st = upload(c, p, hadj, &p.d_hadj))) return st;
+  if ((st = upload(c, p, dadj, &p.d_dadj))) return st;
+  if ((st = upload(c, p, row_ptr, &p.d_arow_ptr))) return st;
+  if ((st = upload(c, p, entries, &p.d_aentry))) return st;
+  if ((st = upload(c, p, scale_all, &p.d_scale))) return st;
+  p.nfitems = (int)items.size();
+  p.nrblocks = (int)rblocks.size();
+  p.nhadj = (int)hadj.size();
+  p.ndadj = (int)dadj.size();
+  void *d = nullptr;
+  if ((st = dev_alloc(c, bop * 16, &d, &p.allocs))) return st;
+  p.d_bop = (uint4 *)d;
+  if ((st = dev_alloc(c, (size_t)nslots * 16 * kRpMax * 4, &d, &p.allocs))) return st;
+  p.d_fpart = (float *)d;
+  if ((st = dev_alloc(c, apart_floats * 4, &d, &p.allocs))) return st;
+  p.d_apart = (float *)d;
+  p.bytes = 0;
+  for (auto &a : p.allocs) p.bytes += a.second;
+  return FK_OK;
+}
+
+hipEvent_t Timing::begin(hipStream_t s) {
+  if (!on.load()) return nullptr;
+  hipEvent_t a = nullptr;
+  if (hipEventCreate(&a) != hipSuccess) return nullptr;
+  (void)hipEventRecord(a, s);
+  return a;
+}
+
+void Timing::end(int kind, hipEvent_t a, hipStream_t s) {
+  if (!a) return;
+  hipEvent_t b = nullptr;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return;
+  }
+  (void)hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(mu);
+  pending.push_back({kind, a, b});
+}
+
+// Run ``launch`` bracketed by timing events of kind ``kind`` when enabled.
+template <typename F>
+static hipError_t timed(Timing *tm, int kind, hipStream_t s, F &&launch) {
+  hipEvent_t a = tm ? tm->begin(s) : nullptr;
+  hipError_t e = launch();
+  if (tm) tm->end(kind, a, s);
+  return e;
+}
+
+hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hipStream_t s,
+                       Timing *tm) {
+  for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
+    const int ncols = std::min(kRpMax, nrep - c0);
+    ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s};
+    const int RP = 16 * L.nt;
+    hipError_t e = timed(tm, FK_K_STAGE, s, [&] {
+      return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop);
+    });
+    if (e != hipSuccess) return e;
+    if (p.kind == FK_HAD)
+      e = timed(tm, FK_K_HAD_FWD, s, [&] {
+        return launch_had_fwd(L, p.d_fitems, p.nfitems, p.d_seg, p.d_gd, p.d_bop, pdf, p.X,
+                              4 * p.maxT_fwd * RP, p.d_fpart);
+      });
+    else
+      e = timed(tm, FK_K_DIS_FWD, s, [&] {
+        return launch_dis_fwd(L, p.d_fitems, p.nfitems, p.d_seg, p.d_gd, p.d_bop,
+                              4 * p.maxT_fwd * RP, p.d_fpart);
+      });
+    if (e != hipSuccess) return e;
+    e = timed(tm, FK_K_FWD_REDUCE, s, [&] {
+      return launch_fwd_reduce(L, p.d_rblocks, p.nrblocks, p.d_slot_idx, p.d_fpart, p.d_scale,
+                               p.kind == FK_HAD ? 0.5f : 1.0f, out);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int nrep, float *g,
+                        int accumulate, hipStream_t s, Timing *tm) {
+  for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
+    const int ncols = std::min(kRpMax, nrep - c0);
+    ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s};
+    const int RP = 16 * L.nt;
+    hipError_t e;
+    if (p.kind == FK_HAD) {
+      e = timed(tm, FK_K_STAGE, s, [&] {
+        return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop);
+      });
+      if (e != hipSuccess) return e;
+      e = timed(tm, FK_K_HAD_ADJ, s, [&] {
+        return launch_had_adj(L, p.d_hadj, p.nhadj, p.d_seg, p.d_gd, p.d_bop, gout, p.d_scale,
+                              p.X, 4 * p.maxT_adj * RP, p.d_apart);
+      });
+    } else {
+      e = timed(tm, FK_K_STAGE, s, [&] {
+        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.ngd_adj, nullptr, gout, p.d_scale,
+                              p.d_bop);
+      });
+      if (e != hipSuccess) return e;
+      e = timed(tm, FK_K_DIS_ADJ, s, [&] {
+        return launch_dis_adj(L, p.d_dadj, p.ndadj, p.d_gd, p.d_bop, 4 * p.maxT_adj * RP,
+                              p.d_apart);
+      });
+    }
+    if (e != hipSuccess) return e;
+    e = timed(tm, FK_K_ADJ_REDUCE, s, [&] {
+      return launch_adj_reduce(L, p.F * p.X, p.d_arow_ptr, p.d_aentry, p.d_apart, accumulate, g);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace fk
+
+// ===========================================================================
+// C entry points
+// ===========================================================================
+extern "C" {
+
+fk_status fk_create(fk_ctx **out, int32_t device, uint64_t hbm_budget_bytes) {
+  if (!out) return set_err(nullptr, FK_E_ARG, "fk_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0)
+    return set_err(nullptr, FK_E_HIP, "fk_create: no HIP device (%s)", hipGetErrorString(e));
+  if (device < 0 || device >= ndev)
+    return set_err(nullptr, FK_E_ARG, "fk_create: device %d out of range [0,%d)", device, ndev);
+  if ((e = hipSetDevice(device)) != hipSuccess)
+    return set_err(nullptr, FK_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+  size_t fre = 0, tot = 0;
+  if ((e = hipMemGetInfo(&fre, &tot)) != hipSuccess)
+    return set_err(nullptr, FK_E_HIP, "hipMemGetInfo: %s", hipGetErrorString(e));
+  auto *c = new fk_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fre);
+  *out = c;
+  return FK_OK;
+}
+
+fk_status fk_serve_stop(fk_ctx *ctx);
+
+fk_status fk_destroy(fk_ctx *ctx) {
+  if (!ctx) return FK_E_ARG;
+  (void)hipSetDevice(ctx->device);
+  fk_serve_stop(ctx);
+  (void)hipDeviceSynchronize();
+  for (auto &kv : ctx->plans) dev_free_all(ctx, kv.second->allocs);
+  for (auto &kv : ctx->covs) dev_free_all(ctx, kv.second->allocs);
+  for (auto &kv : ctx->tables) dev_free_all(ctx, kv.second->allocs);
+  delete ctx;
+  return FK_OK;
+}
+
+const char *fk_last_error(const fk_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+fk_status fk_memory(const fk_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes) {
+  if (!ctx) return FK_E_ARG;
+  if (used_bytes) *used_bytes = ctx->used.load();
+  if (budget_bytes) *budget_bytes = ctx->budget;
+  return FK_OK;
+}
+
+fk_status fk_load_table(fk_ctx *ctx, int32_t kind, int32_t ndata, int32_t nflav, int32_t nx,
+                        const double *xgrid, const uint8_t *mask, const double *fkv,
+                        int32_t store_dtype, fk_table *out) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  if (!out || !xgrid || !mask || !fkv)
+    return set_err(ctx, FK_E_ARG, "fk_load_table: NULL pointer argument");
+  *out = 0;
+  if (kind != FK_DIS && kind != FK_HAD) return set_err(ctx, FK_E_ARG, "fk_load_table: bad kind %d", kind);
+  if (store_dtype != FK_F32 && store_dtype != FK_BF16 && store_dtype != FK_FP8E4M3)
+    return set_err(ctx, FK_E_ARG, "fk_load_table: bad store_dtype %d", store_dtype);
+  if (ndata < 1 || nflav < 1 || nflav > 64 || nx < 2 || nx > kMaxNx)
+    return set_err(ctx, FK_E_SHAPE, "fk_load_table: sizes out of range (ndata=%d nflav=%d nx=%d; "
+                   "need ndata>=1, 1<=nflav<=64, 2<=nx<=%d)", ndata, nflav, nx, kMaxNx);
+  for (int i = 0; i < nx; ++i)
+    if (!(xgrid[i] > 0.0) || !std::isfinite(xgrid[i]) || (i && !(xgrid[i] > xgrid[i - 1])))
+      return set_err(ctx, FK_E_GRID, "fk_load_table: x-grid must be positive and increasing");
+  const int nm = kind == FK_DIS ? nflav : nflav * nflav;
+  int nact = 0;
+  for (int i = 0; i < nm; ++i) nact += mask[i] ? 1 : 0;
+  if (nact == 0) return set_err(ctx, FK_E_SHAPE, "fk_load_table: mask has no active entry");
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  auto t = std::make_unique<Table>();
+  t->kind = kind;
+  t->N = ndata;
+  t->F = nflav;
+  t->X = nx;
+  t->dtype = store_dtype;
+  t->xgrid.assign(xgrid, xgrid + nx);
+  PackedTable pt;
+  try {
+    if (kind == FK_DIS)
+      pack_dis(fkv, mask, ndata, nflav, nx, store_dtype, pt);
+    else
+      pack_had(fkv, mask, ndata, nflav, nx, store_dtype, pt);
+  } catch (const std::exception &ex) {
+    return set_err(ctx, FK_E_HIP, "fk_load_table: packing failed: %s", ex.what());
+  }
+  std::vector<std::pair<void *, size_t>> track;
+  fk_status st = dev_alloc(ctx, pt.fk.size(), &t->d_fk, &track);
+  if (st) return st;
+  t->fk_bytes = pt.fk.size();
+  if (!pt.fkT.empty()) {
+    if ((st = dev_alloc(ctx, pt.fkT.size(), &t->d_fkT, &track))) {
+      dev_free_all(ctx, track);
+      return st;
+    }
+    t->fkT_bytes = pt.fkT.size();
+  }
+  hipError_t e = hipMemcpy(t->d_fk, pt.fk.data(), pt.fk.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && t->d_fkT)
+    e = hipMemcpy(t->d_fkT, pt.fkT.data(), pt.fkT.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free_all(ctx, track);
+    return set_err(ctx, FK_E_HIP, "fk_load_table: copy to device: %s", hipGetErrorString(e));
+  }
+  t->groups = std::move(pt.groups);
+  t->tchunks = std::move(pt.tchunks);
+  t->active = std::move(pt.active);
+  t->scale = std::move(pt.scale);
+  t->nact = pt.nact;
+  t->allocs = std::move(track);
+  auto p = std::make_unique<Plan>();
+  p->kind = kind;
+  p->dtype = store_dtype;
+  p->F = nflav;
+  p->X = nx;
+  p->tables = {0};
+  std::vector<Table *> ts{t.get()};
+  if ((st = build_plan(ctx, *p, ts))) {
+    dev_free_all(ctx, p->allocs);
+    dev_free_all(ctx, t->allocs);
+    return st;
+  }
+  const int64_t id = ctx->next_id++;
+  p->tables = {id};
+  ctx->tables[id] = std::move(t);
+  ctx->plans[id] = std::move(p);
+  *out = id;
+  return FK_OK;
+}
+
+fk_status fk_group_create(fk_ctx *ctx, int32_t ntables, const fk_table *tables, fk_table *out) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  if (!out || !tables || ntables < 1) return set_err(ctx, FK_E_ARG, "fk_group_create: bad arguments");
+  *out = 0;
+  std::vector<Table *> ts;
+  for (int i = 0; i < ntables; ++i) {
+    Table *t = find_table(ctx, tables[i]);
+    if (!t) return set_err(ctx, FK_E_HANDLE, "fk_group_create: table %lld is not loaded", (long long)tables[i]);
+    ts.push_back(t);
+  }
+  for (auto *t : ts) {
+    if (t->kind != ts[0]->kind || t->dtype != ts[0]->dtype || t->F != ts[0]->F || t->X != ts[0]->X)
+      return set_err(ctx, FK_E_SHAPE, "fk_group_create: members differ in kind, dtype, nflav or nx");
+    for (int k = 0; k < t->X; ++k)
+      if (std::fabs(t->xgrid[k] - ts[0]->xgrid[k]) > 1e-12 * std::fabs(ts[0]->xgrid[k]))
+        return set_err(ctx, FK_E_GRID, "fk_group_create: members use different x-grids");
+  }
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  auto p = std::make_unique<Plan>();
+  p->kind = ts[0]->kind;
+  p->dtype = ts[0]->dtype;
+  p->F = ts[0]->F;
+  p->X = ts[0]->X;
+  p->is_group = true;
+  fk_status st = build_plan(ctx, *p, ts);
+  if (st) {
+    dev_free_all(ctx, p->allocs);
+    return st;
+  }
+  p->tables.assign(tables, tables + ntables);
+  for (auto *t : ts) t->group_refs++;
+  const int64_t id = ctx->next_id++;
+  ctx->plans[id] = std::move(p);
+  *out = id;
+  return FK_OK;
+}
+
+fk_status fk_unload_table(fk_ctx *ctx, fk_table table) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  Plan *p = find_plan(ctx, table);
+  if (!p) return set_err(ctx, FK_E_HANDLE, "fk_unload_table: unknown handle %lld", (long long)table);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (p->is_group) {
+    for (auto h : p->tables)
+      if (Table *t = find_table(ctx, h)) t->group_refs--;
+    dev_free_all(ctx, p->allocs);
+    ctx->plans.erase(table);
+    return FK_OK;
+  }
+  Table *t = find_table(ctx, table);
+  if (t && t->busy > 0)
+    return set_err(ctx, FK_E_STATE, "fk_unload_table: table %lld has serving passes in flight",
+                   (long long)table);
+  if (t && t->group_refs > 0)
+    return set_err(ctx, FK_E_STATE, "fk_unload_table: table %lld is used by %d group(s)",
+                   (long long)table, t->group_refs);
+  dev_free_all(ctx, p->allocs);
+  ctx->plans.erase(table);
+  if (t) {
+    dev_free_all(ctx, t->allocs);
+    ctx->tables.erase(table);
+  }
+  return FK_OK;
+}
+
+fk_status fk_table_info(fk_ctx *ctx, fk_table table, int32_t *kind, int32_t *ndata, int32_t *nflav,
+                        int32_t *nx, int32_t *store_dtype, uint64_t *device_bytes) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  Plan *p = find_plan(ctx, table);
+  if (!p) return set_err(ctx, FK_E_HANDLE, "fk_table_info: unknown handle %lld", (long long)table);
+  if (kind) *kind = p->kind;
+  if (ndata) *ndata = p->Ntot;
+  if (nflav) *nflav = p->F;
+  if (nx) *nx = p->X;
+  if (store_dtype) *store_dtype = p->dtype;
+  if (device_bytes) *device_bytes = p->bytes + (p->is_group ? 0 : p->table_bytes);
+  return FK_OK;
+}
+
+static fk_status conv_common(fk_ctx *ctx, fk_table table, int kind, const double *pdf_xgrid,
+                             const float *pdf, int32_t nrep, float *out, void *stream,
+                             const char *name) {
+  if (!ctx) return FK_E_ARG;
+  Plan *p;
+  {
+    Guard g(ctx);
+    p = find_plan(ctx, table);
+    if (!p) return set_err(ctx, FK_E_HANDLE, "%s: unknown handle %lld", name, (long long)table);
+    if (p->kind != kind)
+      return set_err(ctx, FK_E_ARG, "%s: handle %lld holds %s tables", name, (long long)table,
+                     p->kind == FK_DIS ? "DIS" : "hadronic");
+    if (!pdf || !out) return set_err(ctx, FK_E_ARG, "%s: NULL pdf or out", name);
+    if (nrep < 1) return set_err(ctx, FK_E_ARG, "%s: nrep must be >= 1 (got %d)", name, nrep);
+    if (pdf_xgrid) {
+      Table *t = find_table(ctx, p->tables[0]);
+      for (int k = 0; t && k < p->X; ++k)
+        if (!(std::fabs(pdf_xgrid[k] - t->xgrid[k]) <= 1e-12 * std::fabs(t->xgrid[k])))
+          return set_err(ctx, FK_E_GRID, "%s: PDF x-grid differs from the table's at index %d", name, k);
+    }
+  }
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  hipError_t e = run_forward(*p, pdf, nrep, out, (hipStream_t)stream, &ctx->timing);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "%s: launch failed: %s", name, hipGetErrorString(e));
+  return FK_OK;
+}
+
+fk_status fk_conv_dis(fk_ctx *ctx, fk_table table, const double *pdf_xgrid, const float *pdf,
+                      int32_t nrep, float *out, void *stream) {
+  return conv_common(ctx, table, FK_DIS, pdf_xgrid, pdf, nrep, out, stream, "fk_conv_dis");
+}
+
+fk_status fk_conv_had(fk_ctx *ctx, fk_table table, const double *pdf_xgrid, const float *pdf,
+                      int32_t nrep, float *out, void *stream) {
+  return conv_common(ctx, table, FK_HAD, pdf_xgrid, pdf, nrep, out, stream, "fk_conv_had");
+}
+
+fk_status fk_conv_backward(fk_ctx *ctx, fk_table table, const float *pdf, const float *grad_out,
+                           int32_t nrep, float *grad_pdf, int32_t accumulate, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  Plan *p;
+  {
+    Guard g(ctx);
+    p = find_plan(ctx, table);
+    if (!p) return set_err(ctx, FK_E_HANDLE, "fk_conv_backward: unknown handle %lld", (long long)table);
+    if (!grad_out || !grad_pdf || (p->kind == FK_HAD && !pdf))
+      return set_err(ctx, FK_E_ARG, "fk_conv_backward: NULL pointer argument");
+    if (nrep < 1) return set_err(ctx, FK_E_ARG, "fk_conv_backward: nrep must be >= 1");
+  }
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  hipError_t e = run_backward(*p, pdf, grad_out, nrep, grad_pdf, accumulate, (hipStream_t)stream,
+                              &ctx->timing);
+  if (e != hipSuccess)
+    return set_err(ctx, FK_E_HIP, "fk_conv_backward: launch failed: %s", hipGetErrorString(e));
+  return FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// covariance and chi2
+// ---------------------------------------------------------------------------
+fk_status fk_load_covariance(fk_ctx *ctx, int32_t nblocks, const int32_t *block_n,
+                             const double *cov, fk_cov *out) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  if (!out || !block_n || !cov || nblocks < 1)
+    return set_err(ctx, FK_E_ARG, "fk_load_covariance: bad arguments");
+  *out = 0;
+  auto cv = std::make_unique<Cov>();
+  cv->nblocks = nblocks;
+  std::vector<int64_t> off;
+  std::vector<int32_t> roff, rtb, rtr;
+  int64_t o = 0;
+  int r = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    const int n = block_n[b];
+    if (n < 1 || n > 65536) return set_err(ctx, FK_E_SHAPE, "fk_load_covariance: block %d size %d", b, n);
+    cv->n.push_back(n);
+    off.push_back(o);
+    roff.push_back(r);
+    for (int r0 = 0; r0 < n; r0 += 32) {
+      rtb.push_back(b);
+      rtr.push_back(r0);
+    }
+    o += (int64_t)n * n;
+    r += n;
+    cv->maxn = std::max(cv->maxn, n);
+  }
+  cv->ntot = r;
+  cv->nrt = (int)rtb.size();
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  std::vector<std::pair<void *, size_t>> tmp;
+  void *d = nullptr;
+  fk_status st;
+  auto fail = [&](fk_status s) {
+    dev_free_all(ctx, tmp);
+    dev_free_all(ctx, cv->allocs);
+    return s;
+  };
+  if ((st = dev_alloc(ctx, (size_t)o * 8, &d, &tmp))) return fail(st);
+  double *d_a = (double *)d;
+  if ((st = dev_alloc(ctx, (size_t)nblocks * 4, &d, &tmp))) return fail(st);
+  int32_t *d_flag = (int32_t *)d;
+  if ((st = dev_alloc(ctx, (size_t)o * 8, &d, &cv->allocs))) return fail(st);
+  cv->d_linv = (double *)d;
+  if ((st = dev_alloc(ctx, nblocks * 4, &d, &cv->allocs))) return fail(st);
+  cv->d_n = (int32_t *)d;
+  if ((st = dev_alloc(ctx, nblocks * 8, &d, &cv->allocs))) return fail(st);
+  cv->d_off = (int64_t *)d;
+  if ((st = dev_alloc(ctx, nblocks * 4, &d, &cv->allocs))) return fail(st);
+  cv->d_roff = (int32_t *)d;
+  if ((st = dev_alloc(ctx, rtb.size() * 4, &d, &cv->allocs))) return fail(st);
+  cv->d_rt_block = (int32_t *)d;
+  if ((st = dev_alloc(ctx, rtr.size() * 4, &d, &cv->allocs))) return fail(st);
+  cv->d_rt_row = (int32_t *)d;
+  if ((st = dev_alloc(ctx, (size_t)cv->ntot * kRpMax * 8, &d, &cv->allocs))) return fail(st);
+  cv->d_y = (double *)d;
+  if ((st = dev_alloc(ctx, (size_t)cv->nrt * kRpMax * 8, &d, &cv->allocs))) return fail(st);
+  cv->d_part = (double *)d;
+  hipError_t e = hipMemcpy(d_a, cov, (size_t)o * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cv->d_n, cv->n.data(), nblocks * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cv->d_off, off.data(), nblocks * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cv->d_roff, roff.data(), nblocks * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cv->d_rt_block, rtb.data(), rtb.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cv->d_rt_row, rtr.data(), rtr.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(cv->d_linv, 0, (size_t)o * 8);
+  if (e == hipSuccess) e = hipMemset(d_flag, 0, nblocks * 4);
+  if (e == hipSuccess)
+    e = launch_cholesky(nblocks, cv->d_n, cv->d_off, d_a, cv->d_linv, d_flag, cv->maxn, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  std::vector<int32_t> flags(nblocks, 0);
+  if (e == hipSuccess) e = hipMemcpy(flags.data(), d_flag, nblocks * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    set_err(ctx, FK_E_HIP, "fk_load_covariance: %s", hipGetErrorString(e));
+    return fail(FK_E_HIP);
+  }
+  for (int b = 0; b < nblocks; ++b)
+    if (flags[b]) {
+      set_err(ctx, FK_E_NOTPD, "fk_load_covariance: block %d is not positive definite (pivot %d)",
+              b, flags[b] - 1);
+      return fail(FK_E_NOTPD);
+    }
+  dev_free_all(ctx, tmp);
+  cv->bytes = 0;
+  for (auto &a : cv->allocs) cv->bytes += a.second;
+  const int64_t id = ctx->next_id++;
+  ctx->covs[id] = std::move(cv);
+  *out = id;
+  return FK_OK;
+}
+
+fk_status fk_unload_covariance(fk_ctx *ctx, fk_cov cov) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  auto it = ctx->covs.find(cov);
+  if (it == ctx->covs.end()) return set_err(ctx, FK_E_HANDLE, "fk_unload_covariance: unknown handle");
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  dev_free_all(ctx, it->second->allocs);
+  ctx->covs.erase(it);
+  return FK_OK;
+}
+
+fk_status fk_chi2(fk_ctx *ctx, fk_cov cov, const float *sigma, const double *data, int32_t nrep,
+                  double *chi2, float *dchi2_dsigma, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  Cov *cv;
+  {
+    Guard g(ctx);
+    auto it = ctx->covs.find(cov);
+    if (it == ctx->covs.end()) return set_err(ctx, FK_E_HANDLE, "fk_chi2: unknown covariance handle");
+    cv = it->second.get();
+    if (!sigma || !data || !chi2) return set_err(ctx, FK_E_ARG, "fk_chi2: NULL pointer argument");
+    if (nrep < 1) return set_err(ctx, FK_E_ARG, "fk_chi2: nrep must be >= 1");
+  }
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
+    const int ncols = std::min(kRpMax, nrep - c0);
+    hipEvent_t ta = ctx->timing.begin((hipStream_t)stream);
+    hipError_t e = launch_chi2(cv->nblocks, cv->nrt, cv->d_rt_block, cv->d_rt_row, cv->d_n,
+                               cv->d_off, cv->d_roff, cv->d_linv, sigma, data, nrep, c0, ncols,
+                               cv->d_y, cv->d_part, chi2, dchi2_dsigma, (hipStream_t)stream);
+    ctx->timing.end(FK_K_CHI2, ta, (hipStream_t)stream);
+    if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_chi2: launch failed: %s", hipGetErrorString(e));
+  }
+  return FK_OK;
+}
+
+fk_status fk_timing_enable(fk_ctx *ctx, int32_t enable) {
+  if (!ctx) return FK_E_ARG;
+  ctx->timing.on = enable != 0;
+  return FK_OK;
+}
+
+fk_status fk_timing_read(fk_ctx *ctx, double *total_ms, int64_t *launches) {
+  if (!ctx) return FK_E_ARG;
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  Timing &T = ctx->timing;
+  std::lock_guard<std::mutex> lk(T.mu);
+  hipError_t err = hipSuccess;
+  for (auto &r : T.pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e == hipSuccess) {
+      T.total[r.kind] += ms;
+      T.count[r.kind] += 1;
+    } else if (err == hipSuccess) {
+      err = e;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  T.pending.clear();
+  for (int k = 0; k < FK_K_COUNT; ++k) {
+    if (total_ms) total_ms[k] = T.total[k];
+    if (launches) launches[k] = T.count[k];
+    T.total[k] = 0.0;
+    T.count[k] = 0;
+  }
+  if (err != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_timing_read: %s", hipGetErrorString(err));
+  return FK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Host runtime of the fkconv library: context, device-memory budget, table
+// registry and launch plans.
+#pragma once
+
+#include <atomic>
+#include <cstdarg>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fk_internal.h"
+#include "pack.h"
+
+struct fk_serve;  // serving loop (serve.cpp)
+
+namespace fk {
+
+// A loaded dataset.
+struct Table {
+  int kind = 0, N = 0, F = 0, X = 0, dtype = 0;
+  std::vector<double> xgrid;
+  std::vector<GroupPlan> groups;
+  std::vector<TChunk> tchunks;
+  std::vector<int> active;
+  std::vector<float> scale;
+  int nact = 0;
+  void *d_fk = nullptr, *d_fkT = nullptr;
+  size_t fk_bytes = 0, fkT_bytes = 0;
+  int64_t fallback = 0;
+  int group_refs = 0;
+  int busy = 0;  // serving passes in flight on this table
+  std::vector<std::pair<void *, size_t>> allocs;
+};
+
+// Everything one conv/backward call on a table or a group needs.
+struct Plan {
+  int kind = 0, dtype = 0, F = 0, X = 0, Ntot = 0;
+  bool is_group = false;
+  std::vector<int64_t> tables;
+  std::vector<int> row0;
+  // device descriptors
+  GroupDesc *d_gd = nullptr;
+  int ngd_fwd = 0, ngd_adj = 0;  // forward descriptors, then adjoint-only ones
+  SegRef *d_seg = nullptr;
+  FwdItem *d_fitems = nullptr;
+  int nfitems = 0;
+  RedBlock *d_rblocks = nullptr;
+  int nrblocks = 0;
+  int32_t *d_slot_idx = nullptr;
+  HadAdjItem *d_hadj = nullptr;
+  int nhadj = 0;
+  DisAdjItem *d_dadj = nullptr;
+  int ndadj = 0;
+  int32_t *d_arow_ptr = nullptr;
+  int64_t *d_aentry = nullptr;
+  float *d_scale = nullptr;
+  // scratch
+  uint4 *d_bop = nullptr;
+  float *d_fpart = nullptr, *d_apart = nullptr;
+  int maxT_fwd = 1, maxT_adj = 1;
+  // bookkeeping
+  std::vector<std::pair<void *, size_t>> allocs;
+  uint64_t bytes = 0;
+  uint64_t table_bytes = 0;  // device bytes of the member tables
+};
+
+// Optional per-kernel timing with event pairs on the launch stream.
+struct Timing {
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::mutex mu;
+  std::atomic<bool> on{false};
+  std::vector<Rec> pending;
+  double total[FK_K_COUNT] = {};
+  int64_t count[FK_K_COUNT] = {};
+  // bracket one launch: begin() before, end() after
+  hipEvent_t begin(hipStream_t s);
+  void end(int kind, hipEvent_t a, hipStream_t s);
+};
+
+struct Cov {
+  int nblocks = 0, ntot = 0, maxn = 0, nrt = 0;
+  std::vector<int> n;
+  double *d_linv = nullptr;
+  int32_t *d_n = nullptr, *d_roff = nullptr, *d_rt_block = nullptr, *d_rt_row = nullptr;
+  int64_t *d_off = nullptr;
+  double *d_y = nullptr, *d_part = nullptr;
+  std::vector<std::pair<void *, size_t>> allocs;
+  uint64_t bytes = 0;
+};
+
+}  // namespace fk
+
+struct fk_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  std::atomic<uint64_t> used{0};
+  std::mutex mu;           // registry and error string
+  std::string err;
+  int64_t next_id = 1;
+  std::map<int64_t, std::unique_ptr<fk::Table>> tables;
+  std::map<int64_t, std::unique_ptr<fk::Plan>> plans;  // table handles and group handles
+  std::map<int64_t, std::unique_ptr<fk::Cov>> covs;
+  fk_serve *serve = nullptr;
+  fk::Timing timing;
+};
+
+namespace fk {
+
+fk_status set_err(fk_ctx *c, fk_status code, const char *fmt, ...);
+fk_status dev_alloc(fk_ctx *c, size_t bytes, void **p, std::vector<std::pair<void *, size_t>> *track);
+void dev_free_all(fk_ctx *c, std::vector<std::pair<void *, size_t>> &track);
+Plan *find_plan(fk_ctx *c, int64_t h);
+Table *find_table(fk_ctx *c, int64_t h);
+
+// Launch the forward or the adjoint of ``plan`` (no validation, no locking).
+hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hipStream_t s,
+                       Timing *tm = nullptr);
+hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int nrep, float *g,
+                        int accumulate, hipStream_t s, Timing *tm = nullptr);
+int pick_nt(int ncols);
+
+}  // namespace fk

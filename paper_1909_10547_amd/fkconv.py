@@ -1,0 +1,354 @@
+"""Python binding of the fkconv C ABI (``include/fkconv.h``).
+
+Argument marshalling only: numpy arrays become host pointers, torch CUDA
+tensors become device pointers, the current torch stream becomes the HIP
+stream.  Every computation runs in ``lib/libfkconv.so``; when that library
+is missing this module raises instead of falling back to anything else.
+The functions keep the C names.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libfkconv.so")
+_lib = None
+
+FK_OK = 0
+FK_E_ARG, FK_E_SHAPE, FK_E_GRID, FK_E_HANDLE, FK_E_BUDGET = -1, -2, -3, -4, -5
+FK_E_TOO_LARGE, FK_E_HIP, FK_E_NOTPD, FK_E_STATE, FK_E_QUEUE_FULL = -6, -7, -8, -9, -10
+FK_DIS, FK_HAD = 1, 2
+FK_F32, FK_BF16, FK_FP8E4M3 = 0, 1, 2
+FK_QUEUED, FK_RUNNING, FK_DONE, FK_FAILED = 0, 1, 2, 3
+
+DTYPES = {"f32": FK_F32, "bf16": FK_BF16, "e4m3": FK_FP8E4M3}
+
+# name -> (restype, argtypes)
+_P, _I32, _I64, _U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PU64 = ctypes.POINTER(ctypes.c_uint64)
+
+
+class fk_request(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_int64), ("nrep", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("pdf", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+SIGNATURES = {
+    "fk_create": (_I32, [ctypes.POINTER(_P), _I32, _U64]),
+    "fk_destroy": (_I32, [_P]),
+    "fk_last_error": (ctypes.c_char_p, [_P]),
+    "fk_memory": (_I32, [_P, _PU64, _PU64]),
+    "fk_load_table": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _PI64]),
+    "fk_unload_table": (_I32, [_P, _I64]),
+    "fk_group_create": (_I32, [_P, _I32, _P, _PI64]),
+    "fk_table_info": (_I32, [_P, _I64, _PI32, _PI32, _PI32, _PI32, _PI32, _PU64]),
+    "fk_conv_dis": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
+    "fk_conv_had": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
+    "fk_conv_backward": (_I32, [_P, _I64, _P, _P, _I32, _P, _I32, _P]),
+    "fk_load_covariance": (_I32, [_P, _I32, _P, _P, _PI64]),
+    "fk_unload_covariance": (_I32, [_P, _I64]),
+    "fk_chi2": (_I32, [_P, _I64, _P, _P, _I32, _P, _P, _P]),
+    "fk_timing_enable": (_I32, [_P, _I32]),
+    "fk_timing_read": (_I32, [_P, _P, _P]),
+    "fk_serve_start": (_I32, [_P, _I32, _I32, _U64]),
+    "fk_serve_stop": (_I32, [_P]),
+    "fk_table_set_fallback": (_I32, [_P, _I64, _I64]),
+    "fk_submit": (_I32, [_P, ctypes.POINTER(fk_request), _PI64]),
+    "fk_poll": (_I32, [_P, _I64, _PI32]),
+    "fk_ticket_times": (_I32, [_P, _I64, _PU64, _PU64, _PU64]),
+}
+
+
+class FKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fkconv error {code}: {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libfkconv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is not built; run __graft_entry__.build() "
+                               "or python -m paper_1909_10547_amd.build")
+        l = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(ctx, st: int):
+    if st != FK_OK:
+        msg = lib().fk_last_error(ctx)
+        raise FKError(st, msg.decode() if msg else "")
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype_name: str, what: str):
+    import torch
+    want = {"f32": torch.float32, "f64": torch.float64}[dtype_name]
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != want or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {want} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+def fk_create(device: int = 0, hbm_budget_bytes: int = 0):
+    ctx = ctypes.c_void_p()
+    st = lib().fk_create(ctypes.byref(ctx), device, hbm_budget_bytes)
+    if st != FK_OK:
+        raise FKError(st, lib().fk_last_error(None).decode())
+    return ctx
+
+
+def fk_destroy(ctx):
+    _check(ctx, lib().fk_destroy(ctx))
+
+
+def fk_last_error(ctx) -> str:
+    m = lib().fk_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def fk_memory(ctx):
+    u, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, lib().fk_memory(ctx, ctypes.byref(u), ctypes.byref(b)))
+    return u.value, b.value
+
+
+# ---------------------------------------------------------------------------
+# tables
+# ---------------------------------------------------------------------------
+
+def fk_load_table(ctx, kind: int, xgrid, mask, fk, store_dtype) -> int:
+    """fk: DIS [N][nact][X] or hadronic [N][npairs][X][X] float64 (active blocks)."""
+    if isinstance(store_dtype, str):
+        store_dtype = DTYPES[store_dtype]
+    xg = np.ascontiguousarray(xgrid, dtype=np.float64)
+    mk = np.ascontiguousarray(mask, dtype=np.uint8)
+    fkv = np.ascontiguousarray(fk, dtype=np.float64)
+    nflav = mk.shape[0]
+    h = ctypes.c_int64()
+    _check(ctx, lib().fk_load_table(ctx, kind, fkv.shape[0], nflav, xg.shape[0], _hptr(xg),
+                                    _hptr(mk), _hptr(fkv), store_dtype, ctypes.byref(h)))
+    return h.value
+
+
+def fk_unload_table(ctx, table: int):
+    _check(ctx, lib().fk_unload_table(ctx, table))
+
+
+def fk_group_create(ctx, tables: Sequence[int]) -> int:
+    arr = np.ascontiguousarray(tables, dtype=np.int64)
+    h = ctypes.c_int64()
+    _check(ctx, lib().fk_group_create(ctx, len(arr), _hptr(arr), ctypes.byref(h)))
+    return h.value
+
+
+def fk_table_info(ctx, table: int) -> dict:
+    v = [ctypes.c_int32() for _ in range(5)]
+    b = ctypes.c_uint64()
+    _check(ctx, lib().fk_table_info(ctx, table, *[ctypes.byref(x) for x in v], ctypes.byref(b)))
+    return dict(kind=v[0].value, ndata=v[1].value, nflav=v[2].value, nx=v[3].value,
+                store_dtype=v[4].value, device_bytes=b.value)
+
+
+# ---------------------------------------------------------------------------
+# convolutions
+# ---------------------------------------------------------------------------
+
+def _conv(fn, ctx, table, pdf, out, pdf_xgrid, stream):
+    import torch
+    info = fk_table_info(ctx, table)
+    if pdf.dim() != 3 or pdf.shape[0] != info["nflav"] or pdf.shape[1] != info["nx"]:
+        raise ValueError(f"pdf must be [{info['nflav']}][{info['nx']}][R], got {tuple(pdf.shape)}")
+    R = pdf.shape[2]
+    if out is None:
+        out = torch.empty((info["ndata"], R), dtype=torch.float32, device=pdf.device)
+    if tuple(out.shape) != (info["ndata"], R):
+        raise ValueError(f"out must be [{info['ndata']}][{R}]")
+    xg = None
+    if pdf_xgrid is not None:
+        xg = np.ascontiguousarray(pdf_xgrid, dtype=np.float64)
+        if xg.shape != (info["nx"],):
+            raise ValueError("pdf_xgrid has the wrong length")
+    _check(ctx, fn(ctx, table, _hptr(xg) if xg is not None else None,
+                   _dptr(pdf, "f32", "pdf"), R, _dptr(out, "f32", "out"), _stream(stream)))
+    return out
+
+
+def fk_conv_dis(ctx, table: int, pdf, out=None, pdf_xgrid=None, stream=None):
+    return _conv(lib().fk_conv_dis, ctx, table, pdf, out, pdf_xgrid, stream)
+
+
+def fk_conv_had(ctx, table: int, pdf, out=None, pdf_xgrid=None, stream=None):
+    return _conv(lib().fk_conv_had, ctx, table, pdf, out, pdf_xgrid, stream)
+
+
+def fk_conv_backward(ctx, table: int, pdf, grad_out, grad_pdf=None, accumulate=False,
+                     stream=None):
+    import torch
+    info = fk_table_info(ctx, table)
+    R = grad_out.shape[1]
+    if tuple(grad_out.shape) != (info["ndata"], R):
+        raise ValueError(f"grad_out must be [{info['ndata']}][R]")
+    if grad_pdf is None:
+        grad_pdf = torch.empty((info["nflav"], info["nx"], R), dtype=torch.float32,
+                               device=grad_out.device)
+    if tuple(grad_pdf.shape) != (info["nflav"], info["nx"], R):
+        raise ValueError("grad_pdf has the wrong shape")
+    pp = None
+    if pdf is not None:
+        if tuple(pdf.shape) != (info["nflav"], info["nx"], R):
+            raise ValueError("pdf has the wrong shape")
+        pp = _dptr(pdf, "f32", "pdf")
+    _check(ctx, lib().fk_conv_backward(ctx, table, pp, _dptr(grad_out, "f32", "grad_out"), R,
+                                       _dptr(grad_pdf, "f32", "grad_pdf"), 1 if accumulate else 0,
+                                       _stream(stream)))
+    return grad_pdf
+
+
+# ---------------------------------------------------------------------------
+# chi2
+# ---------------------------------------------------------------------------
+
+def fk_load_covariance(ctx, blocks: Sequence[np.ndarray]) -> int:
+    n = np.asarray([b.shape[0] for b in blocks], dtype=np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.ascontiguousarray(b, dtype=np.float64).ravel()
+                                                for b in blocks]))
+    h = ctypes.c_int64()
+    _check(ctx, lib().fk_load_covariance(ctx, len(n), _hptr(n), _hptr(flat), ctypes.byref(h)))
+    return h.value
+
+
+def fk_unload_covariance(ctx, cov: int):
+    _check(ctx, lib().fk_unload_covariance(ctx, cov))
+
+
+def fk_chi2(ctx, cov: int, sigma, data, chi2=None, dchi2_dsigma=None, want_grad=True,
+            stream=None):
+    import torch
+    R = sigma.shape[1]
+    if chi2 is None:
+        chi2 = torch.empty(R, dtype=torch.float64, device=sigma.device)
+    if want_grad and dchi2_dsigma is None:
+        dchi2_dsigma = torch.empty_like(sigma)
+    _check(ctx, lib().fk_chi2(ctx, cov, _dptr(sigma, "f32", "sigma"), _dptr(data, "f64", "data"), R,
+                              _dptr(chi2, "f64", "chi2"),
+                              _dptr(dchi2_dsigma, "f32", "dchi2_dsigma") if want_grad else None,
+                              _stream(stream)))
+    return chi2, (dchi2_dsigma if want_grad else None)
+
+
+# ---------------------------------------------------------------------------
+# kernel timing
+# ---------------------------------------------------------------------------
+KERNEL_KINDS = ["stage", "had_fwd", "dis_fwd", "fwd_reduce", "had_adj", "dis_adj",
+                "adj_reduce", "chi2"]
+
+
+def fk_timing_enable(ctx, enable: bool = True):
+    _check(ctx, lib().fk_timing_enable(ctx, 1 if enable else 0))
+
+
+def fk_timing_read(ctx) -> dict:
+    """{kind: (total_ms, launches)} since the previous read."""
+    ms = np.zeros(len(KERNEL_KINDS), dtype=np.float64)
+    n = np.zeros(len(KERNEL_KINDS), dtype=np.int64)
+    _check(ctx, lib().fk_timing_read(ctx, _hptr(ms), _hptr(n)))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def fk_serve_start(ctx, nslots: int = 64, nstreams: int = 4, request_budget_bytes: int = 256 << 20):
+    _check(ctx, lib().fk_serve_start(ctx, nslots, nstreams, request_budget_bytes))
+
+
+def fk_serve_stop(ctx):
+    _check(ctx, lib().fk_serve_stop(ctx))
+
+
+def fk_table_set_fallback(ctx, table: int, fallback: int):
+    _check(ctx, lib().fk_table_set_fallback(ctx, table, fallback))
+
+
+def fk_submit(ctx, table: int, pdf, out, precision: int = FK_BF16, tag: int = 0) -> int:
+    req = fk_request(table=table, nrep=pdf.shape[2], precision=precision,
+                     pdf=_dptr(pdf, "f32", "pdf").value, out=_dptr(out, "f32", "out").value,
+                     tag=tag)
+    t = ctypes.c_int64()
+    _check(ctx, lib().fk_submit(ctx, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def fk_poll(ctx, ticket: int) -> int:
+    s = ctypes.c_int32()
+    _check(ctx, lib().fk_poll(ctx, ticket, ctypes.byref(s)))
+    return s.value
+
+
+def fk_ticket_times(ctx, ticket: int):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, lib().fk_ticket_times(ctx, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Context:
+    """Owns an fk_ctx; ``with Context() as c: ...`` destroys it on exit."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.ctx = fk_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.ctx is not None:
+            fk_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def load(self, table, store_dtype="bf16") -> int:
+        """Load a synth.DisTable / synth.HadTable."""
+        kind = FK_HAD if table.mask.ndim == 2 else FK_DIS
+        return fk_load_table(self.ctx, kind, table.xgrid, table.mask, table.fk, store_dtype)

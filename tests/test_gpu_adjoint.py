@@ -1,0 +1,177 @@
+"""GPU parity of the hand-written adjoint (vector-Jacobian product with
+respect to the PDF) against the oracle's analytic gradient, plus exact
+central finite differences of the GPU forward (the observables are linear
+or quadratic in f, so central differences carry no truncation error).
+
+Gates as for the forward pass: FP32 normwise <= 1e-5; BF16 normwise <= 1e-5
+against the stored-operand mode and componentwise within the two-factor
+rounding bound against FP64."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_10547_amd import autograd, fkconv, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -8  # bfloat16 unit roundoff (8 significant bits)
+COMP = 2 * U + U * U + 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fkconv.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def gpu_grad(c, h, kind, pdf32, gbar32, accumulate=None):
+    g0 = None if accumulate is None else dev(accumulate)
+    g = fkconv.fk_conv_backward(c.ctx, h, dev(pdf32) if kind == "had" else None, dev(gbar32),
+                                grad_pdf=g0, accumulate=accumulate is not None)
+    torch.cuda.synchronize()
+    return g.cpu().double().numpy()
+
+
+def check_grad(c, kind, tab, pdf, gbar, fmt, label):
+    pdf32, gbar32 = f32(pdf), f32(gbar)
+    h = c.load(tab, fmt)
+    try:
+        got = gpu_grad(c, h, kind, pdf32, gbar32)
+    finally:
+        fkconv.fk_unload_table(c.ctx, h)
+    if kind == "had":
+        ref = oracle.had_grad(tab.mask, tab.fk, pdf32, gbar32)
+    else:
+        ref = oracle.dis_grad(tab.mask, tab.fk, gbar32)
+    e = oracle.normwise_rel(got, ref)
+    msg = f"{label} {kind} adjoint {fmt} N={tab.ndata} R={pdf.shape[2]}: normwise vs FP64 {e:.3e}"
+    if fmt == "f32":
+        assert e <= 1e-5, msg
+    else:
+        if kind == "had":
+            q = oracle.had_grad_quantized(tab.mask, tab.fk, pdf32, gbar32, fmt)
+            absterms = oracle.had_grad(tab.mask, np.abs(tab.fk), np.abs(pdf32), np.abs(gbar32))
+        else:
+            q = oracle.dis_grad_quantized(tab.mask, tab.fk, gbar32, fmt)
+            absterms = oracle.dis_grad(tab.mask, np.abs(tab.fk), np.abs(gbar32))
+        eq = oracle.normwise_rel(got, q)
+        comp = float(np.max(np.abs(got - ref) / np.where(absterms > 0, absterms, 1.0)))
+        msg += f" stored-operand {eq:.3e} componentwise {comp:.3e}"
+        assert eq <= 1e-5, msg
+        assert comp <= COMP, msg
+    say(msg)
+
+
+@pytest.mark.parametrize("R", [1, 100, 130])
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_dis_adjoint(ctx, R, fmt):
+    w = synth.config1(scale=0.2)
+    tab = w.table(4)
+    rng = np.random.default_rng(R)
+    check_grad(ctx, "dis", tab, w.pdf(R), rng.normal(size=(tab.ndata, R)), fmt, "config1-d4")
+
+
+@pytest.mark.parametrize("R", [1, 100, 130])
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_had_adjoint(ctx, R, fmt):
+    w = synth.config2(scale=0.05)
+    tab = w.table(3)
+    rng = np.random.default_rng(R)
+    check_grad(ctx, "had", tab, w.pdf(R), rng.normal(size=(tab.ndata, R)), fmt, "config2-d3")
+
+
+def test_had_adjoint_general_table(ctx):
+    rng = np.random.default_rng(9)
+    xg = synth.xgrid_geom(1e-6, 0.95, 20)
+    t = synth.draw_general_had_table(rng, xg, 41, npairs=37)
+    f = synth.sample_pdf(synth.draw_pdf_params(rng), xg, 7, 0.05, rng)
+    for fmt in ("f32", "bf16"):
+        check_grad(ctx, "had", t, f, rng.normal(size=(41, 7)), fmt, "general")
+
+
+def test_accumulate_and_groups(ctx):
+    w = synth.config2(scale=0.03)
+    tabs = [w.table(d) for d in range(3)]
+    pdf32 = f32(w.pdf(16))
+    rng = np.random.default_rng(3)
+    N = sum(t.ndata for t in tabs)
+    gbar32 = f32(rng.normal(size=(N, 16)))
+    g0 = f32(rng.normal(size=(14, 50, 16)))
+    hs = [ctx.load(t, "f32") for t in tabs]
+    grp = fkconv.fk_group_create(ctx.ctx, hs)
+    got = gpu_grad(ctx, grp, "had", pdf32, gbar32, accumulate=g0)
+    ref = g0.copy()
+    off = 0
+    for t in tabs:
+        ref += oracle.had_grad(t.mask, t.fk, pdf32, gbar32[off:off + t.ndata])
+        off += t.ndata
+    e = oracle.normwise_rel(got, ref)
+    say(f"group adjoint with accumulate: {e:.3e}")
+    assert e <= 1e-5
+    fkconv.fk_unload_table(ctx.ctx, grp)
+    for h in hs:
+        fkconv.fk_unload_table(ctx.ctx, h)
+    # DIS group
+    w1 = synth.config1(scale=0.1)
+    dt = [w1.table(d) for d in range(5)]
+    hs = [ctx.load(t, "f32") for t in dt]
+    grp = fkconv.fk_group_create(ctx.ctx, hs)
+    N = sum(t.ndata for t in dt)
+    gbar32 = f32(rng.normal(size=(N, 16)))
+    got = gpu_grad(ctx, grp, "dis", pdf32, gbar32)
+    ref = np.zeros_like(got)
+    off = 0
+    for t in dt:
+        ref += oracle.dis_grad(t.mask, t.fk, gbar32[off:off + t.ndata])
+        off += t.ndata
+    e = oracle.normwise_rel(got, ref)
+    say(f"DIS group adjoint: {e:.3e}")
+    assert e <= 1e-5
+    fkconv.fk_unload_table(ctx.ctx, grp)
+    for h in hs:
+        fkconv.fk_unload_table(ctx.ctx, h)
+
+
+def test_central_differences_of_the_gpu_forward(ctx):
+    # L(f) = sum gbar * sigma(f) is quadratic in f, so the central difference
+    # along any direction v equals <grad L, v> exactly; a large step keeps the
+    # FP32 rounding noise of the forward small.
+    w = synth.config2(scale=0.04)
+    tab = w.table(5)
+    pdf32 = f32(w.pdf(8))
+    rng = np.random.default_rng(11)
+    gbar = dev(f32(rng.normal(size=(tab.ndata, 8))))
+    h = ctx.load(tab, "f32")
+    x = dev(pdf32).requires_grad_(True)
+    L = (autograd.fk_conv(ctx.ctx, h, x) * gbar).sum()
+    L.backward()
+    g = x.grad.double()
+    for k in range(4):
+        v = dev(f32(rng.normal(size=pdf32.shape) * np.abs(pdf32)))
+        step = 0.25
+        sp = fkconv.fk_conv_had(ctx.ctx, h, x.detach() + step * v).double()
+        sm = fkconv.fk_conv_had(ctx.ctx, h, x.detach() - step * v).double()
+        fd = float(((sp - sm) * gbar.double()).sum() / (2 * step))
+        an = float((g * v.double()).sum())
+        # FP32 forward errors are ~1e-6 of |sigma|; bound their effect
+        noise = 1e-5 * float(((sp.abs() + sm.abs()) * gbar.double().abs()).sum()) / (2 * step)
+        say(f"direction {k}: FD {fd:.6e} adjoint {an:.6e} noise bound {noise:.1e}")
+        assert abs(fd - an) <= noise + 1e-5 * abs(an)
+    fkconv.fk_unload_table(ctx.ctx, h)

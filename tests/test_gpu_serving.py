@@ -1,0 +1,110 @@
+"""Serving loop: continuous batching of requests with mixed tables and
+replica counts.  Every request's result must be bitwise the same as the
+same request run alone through fk_conv_*, and match the FP64 oracle within
+its format's tolerance; FP32 requests on a BF16 table are routed to the
+linked FP32 table."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_10547_amd import fkconv, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_mixed_requests_equal_alone_runs():
+    wd = synth.config1(scale=0.15)
+    wh = synth.config2(scale=0.04)
+    cat = [("dis", wd.table(0)), ("dis", wd.table(1)), ("had", wh.table(0)), ("had", wh.table(1)),
+           ("had", wh.table(2))]
+    rng = np.random.default_rng(4)
+    with fkconv.Context(0) as c:
+        hb = [c.load(t, "bf16") for _, t in cat]
+        hf = [c.load(t, "f32") for _, t in cat]
+        for b, f in zip(hb, hf):
+            fkconv.fk_table_set_fallback(c.ctx, b, f)
+        fkconv.fk_serve_start(c.ctx, nslots=24, nstreams=3, request_budget_bytes=48 << 20)
+        reqs = []
+        for k in range(160):
+            ti = int(rng.integers(0, len(cat)))
+            R = int(rng.choice([1, 4, 16, 100]))
+            prec = fkconv.FK_F32 if rng.random() < 0.2 else fkconv.FK_BF16
+            pdf = synth.sample_pdf(synth.draw_pdf_params(np.random.default_rng([4, k])), wd.xgrid, R,
+                                   0.05 if R > 1 else 0.0, np.random.default_rng([5, k]))
+            x = torch.from_numpy(pdf.astype(np.float32)).cuda()
+            out = torch.full((cat[ti][1].ndata, R), float("nan"), device="cuda")
+            reqs.append((ti, R, prec, x, out))
+        torch.cuda.synchronize()
+        tickets = [fkconv.fk_submit(c.ctx, hb[ti], x, out, precision=prec) for ti, R, prec, x, out in reqs]
+        t0 = time.time()
+        pending = set(range(len(tickets)))
+        while pending and time.time() - t0 < 60:
+            for i in list(pending):
+                st = fkconv.fk_poll(c.ctx, tickets[i])
+                assert st != fkconv.FK_FAILED
+                if st == fkconv.FK_DONE:
+                    pending.discard(i)
+        assert not pending, f"{len(pending)} requests not done"
+        lat = []
+        for t in tickets:
+            a, b, d = fkconv.fk_ticket_times(c.ctx, t)
+            assert a <= b <= d
+            lat.append((d - a) * 1e-6)
+        say(f"served {len(tickets)} requests in {time.time() - t0:.2f}s; latency p50 {np.percentile(lat, 50):.2f} ms "
+            f"p99 {np.percentile(lat, 99):.2f} ms")
+        fkconv.fk_serve_stop(c.ctx)
+        nchk = 0
+        for (ti, R, prec, x, out) in reqs:
+            kind, tab = cat[ti]
+            h = hf[ti] if prec == fkconv.FK_F32 else hb[ti]
+            fn = fkconv.fk_conv_had if kind == "had" else fkconv.fk_conv_dis
+            alone = fn(c.ctx, h, x)
+            torch.cuda.synchronize()
+            assert torch.equal(alone, out), f"request on table {ti} R={R} differs from its alone run"
+            if nchk < 40:
+                # FP32: the FP64 definition; BF16: the oracle on the same
+                # rounded operands (kernel arithmetic)
+                pdf32 = x.double().cpu().numpy()
+                if prec == fkconv.FK_F32:
+                    ref = (oracle.had if kind == "had" else oracle.dis)(tab.mask, tab.fk, pdf32)
+                else:
+                    ref = (oracle.had_quantized if kind == "had" else oracle.dis_quantized)(
+                        tab.mask, tab.fk, pdf32, "bf16")
+                e = oracle.normwise_rel(out.double().cpu().numpy(), ref)
+                assert e <= 1e-5, (kind, R, prec, e)
+                nchk += 1
+        say("every request equals its alone run bitwise")
+
+
+def test_serving_errors():
+    w = synth.config1(scale=0.1)
+    t = w.table(0)
+    with fkconv.Context(0) as c:
+        h = c.load(t, "bf16")
+        x = torch.zeros((14, 50, 4), device="cuda")
+        out = torch.zeros((t.ndata, 4), device="cuda")
+        with pytest.raises(fkconv.FKError) as e:
+            fkconv.fk_submit(c.ctx, h, x, out)
+        assert e.value.code == fkconv.FK_E_STATE
+        fkconv.fk_serve_start(c.ctx, nslots=4, nstreams=2, request_budget_bytes=1 << 20)
+        with pytest.raises(fkconv.FKError) as e:
+            fkconv.fk_submit(c.ctx, 987654, x, out)
+        assert e.value.code == fkconv.FK_E_HANDLE
+        big = torch.zeros((14, 50, 4000), device="cuda")
+        bigo = torch.zeros((t.ndata, 4000), device="cuda")
+        with pytest.raises(fkconv.FKError) as e:
+            fkconv.fk_submit(c.ctx, h, big, bigo)
+        assert e.value.code == fkconv.FK_E_TOO_LARGE
+        with pytest.raises(fkconv.FKError) as e:
+            fkconv.fk_unload_table(c.ctx, 987654)
+        assert e.value.code == fkconv.FK_E_HANDLE
+        fkconv.fk_serve_stop(c.ctx)
