@@ -93,6 +93,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip DIS/adjoint/chi2 rows")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-bf16", action="store_true",
+                    help="only load the BF16 tables and run the BF16 step (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain device copy of 1 GiB three times (HBM byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -105,6 +109,15 @@ def main() -> int:
     from paper_1909_10547_amd import fkconv, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}))
+        return 0
     t_start = time.perf_counter()
     w = synth.config2(args.scale)
     R = w.nrep
@@ -117,8 +130,15 @@ def main() -> int:
     c = fkconv.Context(0)
     t0 = time.perf_counter()
     hb = [c.load(t, "bf16") for t in tabs]
-    hf = [c.load(t, "f32") for t in tabs]
     gb = fkconv.fk_group_create(c.ctx, hb)
+    if args.profile_bf16:
+        x = torch.from_numpy(pdf64.astype(np.float32)).cuda()
+        for _ in range(args.warmup + args.steps):
+            fkconv.fk_conv_had(c.ctx, gb, x)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_bf16_steps": args.warmup + args.steps}))
+        return 0
+    hf = [c.load(t, "f32") for t in tabs]
     gf = fkconv.fk_group_create(c.ctx, hf)
     log(f"  packed and loaded bf16 + fp32 in {time.perf_counter() - t0:.1f}s")
     Ntot = sum(t.ndata for t in tabs)

@@ -74,32 +74,50 @@ struct Mma<FK_FP8E4M3> {
   }
 };
 
+// Table pointers come from descriptors in memory, so the compiler cannot
+// infer their address space and would emit flat loads, which count against
+// the LDS wait counter as well: every LDS read of the B operand would then
+// wait for the in-flight HBM prefetch.  The tables live in global memory.
+typedef const __attribute__((address_space(1))) u32x4 *gu32x4_ptr;
+__device__ __forceinline__ gu32x4_ptr as_global(const void *p) { return (gu32x4_ptr)p; }
+
 // A operand of one tile: T k-steps of the row block stored unit-major
-// (unit u of row rho at base[u*nv + rho]); rows >= nv and units >= KE are 0.
-__device__ __forceinline__ void load_a(u32x4 (&a)[kTMax], const u32x4 *__restrict__ base, int nv,
-                                       int KE, int T) {
+// (unit u of row rho at base[u*nv + rho]); rows >= nv, units >= KE and
+// k-steps >= T read the zero page ``zp`` (64 zero units, always mapped).
+// Every tile thus issues exactly kTMax loads, so the compiler can wait for
+// one tile precisely while the next tile's loads stay in flight.
+__device__ __forceinline__ void load_a(u32x4 (&a)[kTMax], const u32x4 *base_generic, int nv,
+                                       int KE, const u32x4 *zp_generic) {
+  const gu32x4_ptr base = as_global(base_generic);
+  const gu32x4_ptr zp = as_global(zp_generic);
   const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) {
     const int u = 4 * t + g;
-    a[t] = u32x4{0u, 0u, 0u, 0u};
-    if (t < T && row < nv && u < KE) a[t] = __builtin_nontemporal_load(base + (size_t)u * nv + row);
+    const bool ok = row < nv && u < KE;
+    a[t] = __builtin_nontemporal_load(ok ? base + (size_t)u * nv + row : zp + lane);
   }
 }
 
 // acc[j] += A (16 x 4T units) * B (4T units x 16 columns of tile j); B in
-// LDS as [unit][RP].
+// LDS as [unit][RP].  The B fragments of k-step t+1 are read while the
+// MFMAs of k-step t issue; the scheduling barrier keeps the compiler from
+// hoisting every LDS read of the tile (which would cost NT*4*T registers).
 template <int DT, int NT>
 __device__ __forceinline__ void mma_tile(const u32x4 (&a)[kTMax], int T,
                                          const u32x4 *__restrict__ lb, f32x4 (&acc)[NT]) {
   constexpr int RP = 16 * NT;
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const u32x4 *bp = lb + g * RP + c;
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) {
     if (t < T) {
-      const u32x4 *bp = lb + (4 * t + g) * RP + c;
+      u32x4 b[NT];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) Mma<DT>::run(a[t], bp[16 * j], acc[j]);
+      for (int j = 0; j < NT; ++j) b[j] = bp[(4 * t) * RP + 16 * j];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) Mma<DT>::run(a[t], b[j], acc[j]);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -220,6 +238,33 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// f[a][alpha][c0 + 16j + lane%16] for the epilogue; columns >= ncols (and
+// a row beyond the grid, row == nullptr) read the zero page.
+template <int NT>
+__device__ __forceinline__ void load_f(float (&f)[NT], const float *row, int ncols,
+                                       const u32x4 *zp) {
+  const int c = threadIdx.x & 15;
+  const float *z = (const float *)zp;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int col = 16 * j + c;
+    f[j] = *((row && col < ncols) ? row + col : z + c);
+  }
+}
+
+// One hadronic forward tile: H = A * B for 16 datapoints at one x index,
+// then sacc[r] += H[., r] * f[a][alpha][r] (the fused dot of Eq. (1)).
+template <int DT, int NT>
+__device__ __forceinline__ void fwd_tile(const u32x4 (&a)[kTMax], int T,
+                                         const u32x4 *__restrict__ lb, const float (&f)[NT],
+                                         f32x4 (&sacc)[NT]) {
+  f32x4 acc[NT];
+  zero(acc);
+  mma_tile<DT, NT>(a, T, lb, acc);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) sacc[j] += acc[j] * f[j];
+}
+
 // ---------------------------------------------------------------------------
 // Hadronic forward
 // ---------------------------------------------------------------------------
@@ -228,7 +273,7 @@ __global__ void __launch_bounds__(kThreads)
     had_fwd_kernel(const FwdItem *__restrict__ items, const SegRef *__restrict__ segs,
                    const GroupDesc *__restrict__ gd, const u32x4 *__restrict__ bop,
                    const float *__restrict__ pdf, int R, int c0, int ncols, int nx,
-                   float *__restrict__ part) {
+                   float *__restrict__ part, const u32x4 *zp) {
   constexpr int RP = 16 * NT;
   extern __shared__ u32x4 lds[];
   const FwdItem it = items[blockIdx.x];
@@ -236,44 +281,33 @@ __global__ void __launch_bounds__(kThreads)
   const int nv = min(16, it.ndata - 16 * it.block0);
   f32x4 sacc[NT];
   zero(sacc);
+  // two tiles of the A operand in registers: the next tile's loads are in
+  // flight while one tile is multiplied.  Prefetches beyond the grid read
+  // the zero page, so every iteration issues the same loads.
   u32x4 a0[kTMax], a1[kTMax];
+  float f0[NT], f1[NT];
   for (int s = it.seg0; s < it.seg1; ++s) {
     const SegRef sr = segs[s];
     const int KE = sr.KE, T = (KE + 3) >> 2;
     const int afl = gd[sr.gdesc].a;
     const u32x4 *blk = (const u32x4 *)sr.base + (size_t)it.block0 * nx * KE * 16;
-    if (w < nx) load_a(a0, blk + (size_t)w * KE * nv, nv, KE, T);
+    const float *frow = pdf + (size_t)afl * nx * R + c0;
+    auto fetch = [&](u32x4 (&a)[kTMax], float (&f)[NT], int al) {
+      const bool in = al < nx;
+      load_a(a, in ? blk + (size_t)al * KE * nv : zp, in ? nv : 0, KE, zp);
+      load_f<NT>(f, in ? frow + (size_t)al * R : nullptr, ncols, zp);
+    };
+    constexpr int S = kWaves;
+    fetch(a0, f0, w);
+    fetch(a1, f1, w + S);
     __syncthreads();
     copy_b(lds, bop + gd[sr.gdesc].bop_off, 4 * T * RP);
     __syncthreads();
-    const float *frow = pdf + (size_t)afl * nx * R + c0;
-    for (int al = w; al < nx; al += 2 * kWaves) {
-      const int al1 = al + kWaves;
-      if (al1 < nx) load_a(a1, blk + (size_t)al1 * KE * nv, nv, KE, T);
-      {
-        f32x4 acc[NT];
-        zero(acc);
-        mma_tile<DT, NT>(a0, T, lds, acc);
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const int col = 16 * j + c;
-          const float fv = col < ncols ? frow[(size_t)al * R + col] : 0.f;
-          sacc[j] += acc[j] * fv;
-        }
-      }
-      if (al1 < nx) {
-        const int al2 = al1 + kWaves;
-        if (al2 < nx) load_a(a0, blk + (size_t)al2 * KE * nv, nv, KE, T);
-        f32x4 acc[NT];
-        zero(acc);
-        mma_tile<DT, NT>(a1, T, lds, acc);
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const int col = 16 * j + c;
-          const float fv = col < ncols ? frow[(size_t)al1 * R + col] : 0.f;
-          sacc[j] += acc[j] * fv;
-        }
-      }
+    for (int al = w; al < nx; al += 2 * S) {
+      fwd_tile<DT, NT>(a0, T, lds, f0, sacc);
+      fetch(a0, f0, al + 2 * S);
+      if (al + S < nx) fwd_tile<DT, NT>(a1, T, lds, f1, sacc);
+      fetch(a1, f1, al + 3 * S);
     }
   }
   // combine the waves' partial sums in a fixed order
@@ -298,7 +332,7 @@ template <int DT, int NT>
 __global__ void __launch_bounds__(kThreads)
     dis_fwd_kernel(const FwdItem *__restrict__ items, const SegRef *__restrict__ segs,
                    const GroupDesc *__restrict__ gd, const u32x4 *__restrict__ bop,
-                   float *__restrict__ part) {
+                   float *__restrict__ part, const u32x4 *zp) {
   constexpr int RP = 16 * NT;
   extern __shared__ u32x4 lds[];
   const FwdItem it = items[blockIdx.x];
@@ -308,11 +342,16 @@ __global__ void __launch_bounds__(kThreads)
   const int nv = active ? min(16, it.ndata - 16 * bl) : 0;
   f32x4 sacc[NT];
   zero(sacc);
-  u32x4 a[kTMax];
-  for (int s = it.seg0; s < it.seg1; ++s) {
+  // the tile of the next group is loaded while the current one is multiplied
+  u32x4 a0[kTMax], a1[kTMax];
+  auto fetch = [&](u32x4 (&a)[kTMax], int s) {
+    const SegRef sr = segs[s < it.seg1 ? s : it.seg0];
+    const bool in = active && s < it.seg1;
+    load_a(a, in ? (const u32x4 *)sr.base + (size_t)bl * sr.KE * 16 : zp, in ? nv : 0, sr.KE, zp);
+  };
+  auto step = [&](const u32x4 (&a)[kTMax], int s) {
     const SegRef sr = segs[s];
-    const int KE = sr.KE, T = (KE + 3) >> 2;
-    if (active) load_a(a, (const u32x4 *)sr.base + (size_t)bl * KE * 16, nv, KE, T);
+    const int T = (sr.KE + 3) >> 2;
     __syncthreads();
     copy_b(lds, bop + gd[sr.gdesc].bop_off, 4 * T * RP);
     __syncthreads();
@@ -323,6 +362,14 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
       for (int j = 0; j < NT; ++j) sacc[j] += acc[j];
     }
+  };
+  fetch(a0, it.seg0);
+  fetch(a1, it.seg0 + 1);
+  for (int s = it.seg0; s < it.seg1; s += 2) {
+    step(a0, s);
+    fetch(a0, s + 2);
+    if (s + 1 < it.seg1) step(a1, s + 1);
+    fetch(a1, s + 3);
   }
   if (active) {
     float *dst = part + (size_t)(it.slot0 + w) * 16 * kRpMax;
@@ -363,7 +410,7 @@ __global__ void __launch_bounds__(kThreads)
     had_adj_kernel(const HadAdjItem *__restrict__ items, const SegRef *__restrict__ segs,
                    const GroupDesc *__restrict__ gd, const u32x4 *__restrict__ bop,
                    const float *__restrict__ gout, const float *__restrict__ scale_all, int R,
-                   int c0, int ncols, int nx, float *__restrict__ apart) {
+                   int c0, int ncols, int nx, float *__restrict__ apart, const u32x4 *zp) {
   constexpr int RP = 16 * NT;
   extern __shared__ u32x4 lds[];
   const HadAdjItem it = items[blockIdx.x];
@@ -376,10 +423,16 @@ __global__ void __launch_bounds__(kThreads)
   copy_b(lb, bop + gd[sr.gdesc].bop_off, 4 * T * RP);
   for (int i = threadIdx.x; i < nx * RP; i += kThreads) gacc[i] = 0.f;
   u32x4 a0[kTMax], a1[kTMax];
+  constexpr int S = kWaves;
   for (int bl = it.block0; bl < it.block1; ++bl) {
     const int nv = min(16, it.ndata - 16 * bl);
     const u32x4 *blk = (const u32x4 *)sr.base + (size_t)bl * nx * KE * 16;
-    if (w < nx) load_a(a0, blk + (size_t)w * KE * nv, nv, KE, T);
+    auto fetch = [&](u32x4 (&a)[kTMax], int al) {
+      const bool in = al < nx;
+      load_a(a, in ? blk + (size_t)al * KE * nv : zp, in ? nv : 0, KE, zp);
+    };
+    fetch(a0, w);
+    fetch(a1, w + S);
     __syncthreads();
     for (int i = threadIdx.x; i < 16 * RP; i += kThreads) {
       const int row = i / RP, col = i - row * RP;
@@ -391,15 +444,11 @@ __global__ void __launch_bounds__(kThreads)
       wl[i] = v;
     }
     __syncthreads();
-    for (int al = w; al < nx; al += 2 * kWaves) {
-      const int al1 = al + kWaves;
-      if (al1 < nx) load_a(a1, blk + (size_t)al1 * KE * nv, nv, KE, T);
+    for (int al = w; al < nx; al += 2 * S) {
       had_adj_tile<DT, NT>(a0, T, lb, wl, gacc + al * RP);
-      if (al1 < nx) {
-        const int al2 = al1 + kWaves;
-        if (al2 < nx) load_a(a0, blk + (size_t)al2 * KE * nv, nv, KE, T);
-        had_adj_tile<DT, NT>(a1, T, lb, wl, gacc + al1 * RP);
-      }
+      fetch(a0, al + 2 * S);
+      if (al + S < nx) had_adj_tile<DT, NT>(a1, T, lb, wl, gacc + (al + S) * RP);
+      fetch(a1, al + 3 * S);
     }
   }
   __syncthreads();
@@ -417,7 +466,7 @@ __global__ void __launch_bounds__(kThreads)
 template <int DT, int NT>
 __global__ void __launch_bounds__(kThreads)
     dis_adj_kernel(const DisAdjItem *__restrict__ items, const GroupDesc *__restrict__ gd,
-                   const u32x4 *__restrict__ bop, float *__restrict__ apart) {
+                   const u32x4 *__restrict__ bop, float *__restrict__ apart, const u32x4 *zp) {
   constexpr int RP = 16 * NT;
   extern __shared__ u32x4 lds[];
   const DisAdjItem it = items[blockIdx.x];
@@ -427,7 +476,7 @@ __global__ void __launch_bounds__(kThreads)
   const int tile = it.tile0 + w;
   const int nv = active ? min(16, it.nrows - 16 * tile) : 0;
   u32x4 a[kTMax];
-  if (active) load_a(a, (const u32x4 *)it.base + (size_t)tile * 16 * KE, nv, KE, T);
+  load_a(a, active ? (const u32x4 *)it.base + (size_t)tile * 16 * KE : zp, nv, KE, zp);
   copy_b(lds, bop + gd[it.gdesc].bop_off, 4 * T * RP);
   __syncthreads();
   if (active) {
@@ -529,7 +578,8 @@ hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems,
     auto k = had_fwd_kernel<DTV, NT>;                                                        \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                   \
     hipLaunchKernelGGL(k, dim3(nitems), dim3(kThreads), lds, L.stream, items, segs, gd,      \
-                       (const u32x4 *)bop, pdf, L.R, L.c0, L.ncols, nx, part);               \
+                       (const u32x4 *)bop, pdf, L.R, L.c0, L.ncols, nx, part,                \
+                       (const u32x4 *)L.zero_page);                                          \
   }
 #define FK_HF_DT(DT)           \
   {                            \
@@ -552,7 +602,7 @@ hipError_t launch_dis_fwd(const ConvLaunch &L, const FwdItem *items, int nitems,
     auto k = dis_fwd_kernel<DTV, NT>;                                                      \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                 \
     hipLaunchKernelGGL(k, dim3(nitems), dim3(kThreads), lds, L.stream, items, segs, gd,    \
-                       (const u32x4 *)bop, part);                                          \
+                       (const u32x4 *)bop, part, (const u32x4 *)L.zero_page);              \
   }
 #define FK_DF_DT(DT)           \
   {                            \
@@ -587,7 +637,8 @@ hipError_t launch_had_adj(const ConvLaunch &L, const HadAdjItem *items, int nite
     auto k = had_adj_kernel<DTV, NT>;                                                          \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                     \
     hipLaunchKernelGGL(k, dim3(nitems), dim3(kThreads), lds, L.stream, items, segs, gd,        \
-                       (const u32x4 *)bop, gout, scale_all, L.R, L.c0, L.ncols, nx, apart);    \
+                       (const u32x4 *)bop, gout, scale_all, L.R, L.c0, L.ncols, nx, apart,     \
+                       (const u32x4 *)L.zero_page);                                            \
   }
 #define FK_HA_DT(DT)           \
   {                            \
@@ -610,7 +661,7 @@ hipError_t launch_dis_adj(const ConvLaunch &L, const DisAdjItem *items, int nite
     auto k = dis_adj_kernel<DTV, NT>;                                                      \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                 \
     hipLaunchKernelGGL(k, dim3(nitems), dim3(kThreads), lds, L.stream, items, gd,          \
-                       (const u32x4 *)bop, apart);                                         \
+                       (const u32x4 *)bop, apart, (const u32x4 *)L.zero_page);             \
   }
 #define FK_DA_DT(DT)           \
   {                            \

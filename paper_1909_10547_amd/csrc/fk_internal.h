@@ -107,7 +107,9 @@ struct ConvLaunch {
   int nt;           // column tiles of 16 (RP = 16*nt)
   int ncols, c0, R; // columns of this pass, their offset, caller's row stride
   hipStream_t stream;
+  const void *zero_page;  // kZeroPageBytes of zeros in device memory
 };
+constexpr int kZeroPageBytes = 4096;
 
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
                           const float *gout, const float *scale_all, uint4 *bop);

@@ -298,6 +298,8 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   p.d_fpart = (float *)d;
   if ((st = dev_alloc(c, apart_floats * 4, &d, &p.allocs))) return st;
   p.d_apart = (float *)d;
+  if ((st = dev_alloc(c, kZeroPageBytes, &p.d_zero, &p.allocs))) return st;
+  FK_TRY_HIP(c, hipMemset(p.d_zero, 0, kZeroPageBytes));
   p.bytes = 0;
   for (auto &a : p.allocs) p.bytes += a.second;
   return FK_OK;
@@ -336,7 +338,7 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
                        Timing *tm) {
   for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
     const int ncols = std::min(kRpMax, nrep - c0);
-    ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s};
+    ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
     hipError_t e = timed(tm, FK_K_STAGE, s, [&] {
       return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop);
@@ -366,7 +368,7 @@ hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int 
                         int accumulate, hipStream_t s, Timing *tm) {
   for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
     const int ncols = std::min(kRpMax, nrep - c0);
-    ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s};
+    ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
     hipError_t e;
     if (p.kind == FK_HAD) {

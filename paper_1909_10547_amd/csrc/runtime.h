@@ -59,6 +59,7 @@ struct Plan {
   // scratch
   uint4 *d_bop = nullptr;
   float *d_fpart = nullptr, *d_apart = nullptr;
+  void *d_zero = nullptr;  // kZeroPageBytes of zeros read by lanes outside a tile
   int maxT_fwd = 1, maxT_adj = 1;
   // bookkeeping
   std::vector<std::pair<void *, size_t>> allocs;
