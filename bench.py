@@ -93,6 +93,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip DIS/adjoint/chi2 rows")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving rows")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving: 10k requests at each of 6 rates (default: 2k requests, 2 rates)")
+    ap.add_argument("--no-dis-hbm", action="store_true",
+                    help="skip the large DIS set used for the HBM-bandwidth rows")
+    ap.add_argument("--dis-hbm-gib", type=float, default=2.0,
+                    help="FP32 table size of the large DIS set")
     ap.add_argument("--profile-bf16", action="store_true",
                     help="only load the BF16 tables and run the BF16 step (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -260,6 +267,12 @@ def main() -> int:
     if not args.no_extras:
         log("extra rows: DIS, adjoints, chi2, fit step")
         result["rows"] = extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth)
+    if not args.no_serve:
+        log("serving")
+        result.setdefault("rows", {})["serving"] = serving(c, w, tabs, args, torch, fkconv, synth)
+    if not args.no_dis_hbm:
+        log("large DIS set for HBM bandwidth")
+        result.setdefault("rows", {})["dis_hbm"] = dis_hbm(c, args, torch, fkconv, synth)
 
     fkconv.fk_unload_table(c.ctx, gb)
     fkconv.fk_unload_table(c.ctx, gf)
@@ -267,6 +280,120 @@ def main() -> int:
     result["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(result), flush=True)
     return 0
+
+
+def serving(c, w, had_tabs, args, torch, fkconv, synth):
+    """Continuous batching: the table catalogue of the serving workload (the
+    20 DIS and 10 hadronic datasets plus two DIS and two hadronic tables with
+    N = 2000), BF16 with FP32 fallback copies; requests pick a table uniformly
+    and R uniformly from {1, 4, 16, 100}; 20% ask for FP32.  Capacity is
+    measured closed-loop (everything submitted at once), then Poisson streams
+    at fractions of it; latency = submit -> completion seen by the loop."""
+    import threading
+    sw = synth.config4(1.0)
+    cat = list(sw.catalogue())
+    hb, hf = [], []
+    for kind, t in cat:
+        hb.append(c.load(t, "bf16"))
+        hf.append(c.load(t, "f32"))
+        fkconv.fk_table_set_fallback(c.ctx, hb[-1], hf[-1])
+    nd = [t.ndata for _, t in cat]
+    kinds = [k for k, _ in cat]
+    pools = {R: [torch.from_numpy(sw.request_pdf(R, k).astype(np.float32)).cuda() for k in range(4)]
+             for R in sw.rep_choices}
+    fkconv.fk_serve_start(c.ctx, nslots=256, nstreams=4, request_budget_bytes=512 << 20)
+    rng = np.random.default_rng(4)
+
+    def run(nreq, rate):
+        t_arr, tab, Rs, pseed = sw.requests(nreq, rate if rate else 1.0, len(cat))
+        prec = np.where(rng.random(nreq) < 0.2, fkconv.FK_F32, fkconv.FK_BF16)
+        outs = [torch.empty((nd[tab[i]], int(Rs[i])), dtype=torch.float32, device="cuda")
+                for i in range(nreq)]
+        torch.cuda.synchronize()
+        tickets = [0] * nreq
+        t0 = time.perf_counter()
+        for i in range(nreq):
+            if rate:
+                dt = t_arr[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            x = pools[int(Rs[i])][int(pseed[i]) % 4]
+            while True:
+                try:
+                    tickets[i] = fkconv.fk_submit(c.ctx, hb[tab[i]], x, outs[i], precision=int(prec[i]))
+                    break
+                except fkconv.FKError as e:
+                    if e.code != fkconv.FK_E_QUEUE_FULL:
+                        raise
+                    time.sleep(1e-4)
+        pend = set(range(nreq))
+        while pend:
+            for i in list(pend):
+                if fkconv.fk_poll(c.ctx, tickets[i]) >= fkconv.FK_DONE:
+                    pend.discard(i)
+        wall = time.perf_counter() - t0
+        lat = np.array([(lambda a, b, d: (d - a) * 1e-6)(*fkconv.fk_ticket_times(c.ctx, t)) for t in tickets])
+        dprep = float(sum(nd[tab[i]] * Rs[i] for i in range(nreq)))
+        return {"requests": nreq, "wall_s": wall, "req_per_s": nreq / wall, "dp_rep_per_s": dprep / wall,
+                "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}, \
+            (tab, Rs, prec, outs, pseed)
+
+    res = {}
+    nreq = 10000 if args.serve_full else 2000
+    cap, sample = run(nreq, None)
+    res["closed_loop"] = cap
+    fracs = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2) if args.serve_full else (0.5, 0.9)
+    for f in fracs:
+        r, sample = run(nreq, f * cap["req_per_s"])
+        res[f"rate_{f:g}x"] = r
+    fkconv.fk_serve_stop(c.ctx)
+    # alone-vs-mix: re-run a sample of the last stream's requests alone
+    tab, Rs, prec, outs, pseed = sample
+    same = 0
+    for i in range(0, len(outs), max(1, len(outs) // 200)):
+        h = hf[tab[i]] if prec[i] == fkconv.FK_F32 else hb[tab[i]]
+        fn = fkconv.fk_conv_had if kinds[tab[i]] == "had" else fkconv.fk_conv_dis
+        same += int(torch.equal(fn(c.ctx, h, pools[int(Rs[i])][int(pseed[i]) % 4]), outs[i]))
+    res["alone_equals_mix"] = f"{same} of {len(range(0, len(outs), max(1, len(outs) // 200)))} sampled requests bitwise equal"
+    for h in hb + hf:
+        fkconv.fk_unload_table(c.ctx, h)
+    return res
+
+
+def dis_hbm(c, args, torch, fkconv, synth):
+    """The global-DIS recipe (20 datasets, 9 of 14 flavours, 50 x-points) with
+    every N scaled so the FP32 tables reach --dis-hbm-gib; 20 tables of
+    1e5 datapoints each are far larger than the 256 MB last-level cache, so
+    every step streams from HBM.  Reports GB/s of algorithmic table bytes."""
+    base = synth.config1()
+    per_dp = 9 * 50 * 4
+    scale = args.dis_hbm_gib * (1 << 30) / (per_dp * sum(base.ndata))
+    w = synth.config1(scale)
+    tabs = [w.table(d) for d in range(len(w.ndata))]
+    N = sum(t.ndata for t in tabs)
+    elems = sum(t.fk.size for t in tabs)
+    out = {"ndata": N, "fk_elements": elems, "peak_gbs": PEAK_HBM_GBS}
+    for fmt, nbytes in (("f32", 4), ("bf16", 2)):
+        hs = [c.load(t, fmt) for t in tabs]
+        g = fkconv.fk_group_create(c.ctx, hs)
+        for R in (1, 100):
+            if fmt == "f32" and R == 100:
+                continue
+            x = torch.from_numpy(w.pdf(R).astype(np.float32)).cuda()
+            y = torch.empty((N, R), dtype=torch.float32, device="cuda")
+            fn = lambda: fkconv.fk_conv_dis(c.ctx, g, x, out=y)
+            ms, _ = time_steps(fn, max(5, args.steps // 2), 2, torch)
+            kt = kernel_times(c, fn, max(5, args.steps // 2), torch, fkconv)
+            kms = kt["dis_fwd"][0] / max(kt["dis_fwd"][1], 1)
+            byt = elems * nbytes + N * R * 4
+            out[f"{fmt}_R{R}"] = {"ms_per_step": ms, "kernel_ms": kms,
+                                  "achieved_gbs": byt / (kms * 1e-3) / 1e9,
+                                  "frac": byt / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                  "value": N * R / (ms * 1e-3)}
+        fkconv.fk_unload_table(c.ctx, g)
+        for h in hs:
+            fkconv.fk_unload_table(c.ctx, h)
+    return out
 
 
 def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):

@@ -199,8 +199,10 @@ template <int DT>
 __global__ void __launch_bounds__(kThreads)
     stage_b_kernel(const GroupDesc *__restrict__ gd, const float *__restrict__ pdf,
                    const float *__restrict__ gout, const float *__restrict__ scale_all, int R,
-                   int c0, int ncols, int RP, u32x4 *__restrict__ bop) {
+                   int c0, int ncols, int RP, u32x4 *__restrict__ bop, int *counter) {
   constexpr int E = Mma<DT>::E;
+  // the forward kernel that follows on the stream takes items from *counter
+  if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
   __shared__ int s_row[kMaxSeg], s_start[kMaxSeg + 1];
   const GroupDesc *G = gd + blockIdx.x;
   const int nseg = G->nseg, K = G->K, src_kind = G->src;
@@ -252,76 +254,167 @@ __device__ __forceinline__ void load_f(float (&f)[NT], const float *row, int nco
   }
 }
 
-// One hadronic forward tile: H = A * B for 16 datapoints at one x index,
-// then sacc[r] += H[., r] * f[a][alpha][r] (the fused dot of Eq. (1)).
-template <int DT, int NT>
-__device__ __forceinline__ void fwd_tile(const u32x4 (&a)[kTMax], int T,
-                                         const u32x4 *__restrict__ lb, const float (&f)[NT],
-                                         f32x4 (&sacc)[NT]) {
-  f32x4 acc[NT];
-  zero(acc);
-  mma_tile<DT, NT>(a, T, lb, acc);
+// Workgroup barrier that orders LDS only: global loads in flight (the next
+// tiles of the FK stream) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Two tiles at the same x index alpha: rows = datapoints of two consecutive
+// 16-datapoint blocks (the second may be absent).  Both tiles multiply the
+// same B fragments, which halves the LDS traffic per byte of table.
+struct TilePair {
+  const u32x4 *p0, *p1;
+  int nv0, nv1, KE;
+  const float *frow;  // f[a][alpha][c0..], nullptr for an empty pair
+};
+
+// k-step t of ``n`` into a0[t], a1[t]; lanes outside a tile read the zero page
+__device__ __forceinline__ void refill(u32x4 (&a0)[kTMax], u32x4 (&a1)[kTMax], int t,
+                                       const TilePair &n, const u32x4 *zp_generic) {
+  const gu32x4_ptr zp = as_global(zp_generic);
+  const int lane = threadIdx.x & 63, g = lane >> 4, row = lane & 15;
+  const int u = 4 * t + g;
+  const bool ok0 = row < n.nv0 && u < n.KE;
+  const bool ok1 = row < n.nv1 && u < n.KE;
+  a0[t] = __builtin_nontemporal_load(ok0 ? as_global(n.p0) + (size_t)u * n.nv0 + row : zp + lane);
+  a1[t] = __builtin_nontemporal_load(ok1 ? as_global(n.p1) + (size_t)u * n.nv1 + row : zp + lane);
+}
+
+// MFMAs of the current pair (TT k-steps) with the next pair's loads issued
+// into each k-step's registers as soon as that k-step has been multiplied;
+// k-steps TT..kTMax-1 of the next pair are loaded after the loop.  Every pair
+// issues the same number of loads, so the waits are exact.
+template <int DT, int NT, int TT>
+__device__ __forceinline__ void pair_mma(u32x4 (&a0)[kTMax], u32x4 (&a1)[kTMax],
+                                         const u32x4 *__restrict__ lb, f32x4 (&acc0)[NT],
+                                         f32x4 (&acc1)[NT], const TilePair &nxt,
+                                         float (&fn)[NT], int ncols, const u32x4 *zp) {
+  constexpr int RP = 16 * NT;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const u32x4 *bp = lb + g * RP + c;
 #pragma unroll
-  for (int j = 0; j < NT; ++j) sacc[j] += acc[j] * f[j];
+  for (int t = 0; t < TT; ++t) {
+    u32x4 b[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) b[j] = bp[4 * t * RP + 16 * j];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      Mma<DT>::run(a0[t], b[j], acc0[j]);
+      Mma<DT>::run(a1[t], b[j], acc1[j]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (t == 0) load_f<NT>(fn, nxt.frow, ncols, zp);
+    refill(a0, a1, t, nxt, zp);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int t = TT; t < kTMax; ++t) refill(a0, a1, t, nxt, zp);
 }
 
 // ---------------------------------------------------------------------------
-// Hadronic forward
+// Hadronic forward.  Persistent workgroups take items (two 16-datapoint
+// blocks x a run of row groups) from a counter; wave w owns the x indices
+// alpha = w (mod 4) of both blocks and keeps its running dot products
+// sigma partial sums for the two blocks in registers.
 // ---------------------------------------------------------------------------
 template <int DT, int NT>
 __global__ void __launch_bounds__(kThreads)
-    had_fwd_kernel(const FwdItem *__restrict__ items, const SegRef *__restrict__ segs,
+    had_fwd_kernel(const FwdItem *__restrict__ items, int nitems, const SegRef *__restrict__ segs,
                    const GroupDesc *__restrict__ gd, const u32x4 *__restrict__ bop,
                    const float *__restrict__ pdf, int R, int c0, int ncols, int nx,
-                   float *__restrict__ part, const u32x4 *zp) {
+                   float *__restrict__ part, const u32x4 *zp, int *counter) {
   constexpr int RP = 16 * NT;
+  constexpr int S = kWaves;
   extern __shared__ u32x4 lds[];
-  const FwdItem it = items[blockIdx.x];
+  __shared__ int s_item;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int nv = min(16, it.ndata - 16 * it.block0);
-  f32x4 sacc[NT];
-  zero(sacc);
-  // two tiles of the A operand in registers: the next tile's loads are in
-  // flight while one tile is multiplied.  Prefetches beyond the grid read
-  // the zero page, so every iteration issues the same loads.
   u32x4 a0[kTMax], a1[kTMax];
-  float f0[NT], f1[NT];
-  for (int s = it.seg0; s < it.seg1; ++s) {
-    const SegRef sr = segs[s];
-    const int KE = sr.KE, T = (KE + 3) >> 2;
-    const int afl = gd[sr.gdesc].a;
-    const u32x4 *blk = (const u32x4 *)sr.base + (size_t)it.block0 * nx * KE * 16;
-    const float *frow = pdf + (size_t)afl * nx * R + c0;
-    auto fetch = [&](u32x4 (&a)[kTMax], float (&f)[NT], int al) {
-      const bool in = al < nx;
-      load_a(a, in ? blk + (size_t)al * KE * nv : zp, in ? nv : 0, KE, zp);
-      load_f<NT>(f, in ? frow + (size_t)al * R : nullptr, ncols, zp);
+  float f[NT], fn[NT];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    lds_barrier();
+    const int item = s_item;
+    if (item >= nitems) break;
+    const FwdItem it = items[item];
+    const int bl0 = it.block0;
+    const int nv0 = min(16, it.ndata - 16 * bl0);
+    const int nv1 = it.nblk > 1 ? min(16, it.ndata - 16 * (bl0 + 1)) : 0;
+    auto pair_at = [&](int s, int al) {
+      TilePair p{zp, zp, 0, 0, 1, nullptr};
+      if (s < it.seg1 && al < nx) {
+        const SegRef sr = segs[s];
+        const u32x4 *base = (const u32x4 *)sr.base;
+        p.KE = sr.KE;
+        p.nv0 = nv0;
+        p.nv1 = nv1;
+        p.p0 = base + ((size_t)bl0 * nx * 16 + (size_t)al * nv0) * sr.KE;
+        p.p1 = nv1 ? base + ((size_t)(bl0 + 1) * nx * 16 + (size_t)al * nv1) * sr.KE : zp;
+        p.frow = pdf + ((size_t)gd[sr.gdesc].a * nx + al) * R + c0;
+      }
+      return p;
     };
-    constexpr int S = kWaves;
-    fetch(a0, f0, w);
-    fetch(a1, f1, w + S);
-    __syncthreads();
-    copy_b(lds, bop + gd[sr.gdesc].bop_off, 4 * T * RP);
-    __syncthreads();
-    for (int al = w; al < nx; al += 2 * S) {
-      fwd_tile<DT, NT>(a0, T, lds, f0, sacc);
-      fetch(a0, f0, al + 2 * S);
-      if (al + S < nx) fwd_tile<DT, NT>(a1, T, lds, f1, sacc);
-      fetch(a1, f1, al + 3 * S);
+    f32x4 sacc0[NT], sacc1[NT];
+    zero(sacc0);
+    zero(sacc1);
+    {  // first pair of the item
+      const TilePair p = pair_at(it.seg0, w);
+#pragma unroll
+      for (int t = 0; t < kTMax; ++t) refill(a0, a1, t, p, zp);
+      load_f<NT>(f, p.frow, ncols, zp);
     }
-  }
-  // combine the waves' partial sums in a fixed order
-  __syncthreads();
-  float *red = (float *)lds;
+    for (int s = it.seg0; s < it.seg1; ++s) {
+      const SegRef sr = segs[s];
+      const int T = (sr.KE + 3) >> 2;
+      lds_barrier();
+      copy_b(lds, bop + gd[sr.gdesc].bop_off, 4 * T * RP);
+      lds_barrier();
+      for (int al = w; al < nx; al += S) {
+        const int aln = al + S < nx ? al + S : w;
+        const TilePair nxt = pair_at(al + S < nx ? s : s + 1, aln);
+        f32x4 acc0[NT], acc1[NT];
+        zero(acc0);
+        zero(acc1);
+        switch (T) {
+          case 1: pair_mma<DT, NT, 1>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          case 2: pair_mma<DT, NT, 2>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          case 3: pair_mma<DT, NT, 3>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          case 4: pair_mma<DT, NT, 4>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          case 5: pair_mma<DT, NT, 5>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          case 6: pair_mma<DT, NT, 6>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          case 7: pair_mma<DT, NT, 7>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+          default: pair_mma<DT, NT, 8>(a0, a1, lds, acc0, acc1, nxt, fn, ncols, zp); break;
+        }
 #pragma unroll
-  for (int j = 0; j < NT; ++j)
+        for (int j = 0; j < NT; ++j) {
+          sacc0[j] += acc0[j] * f[j];
+          sacc1[j] += acc1[j] * f[j];
+          f[j] = fn[j];
+        }
+      }
+    }
+    // combine the waves' partial sums in a fixed order, one slot per block
+    lds_barrier();
+    float *red = (float *)lds;  // [block][wave][16][RP]
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[(w * 16 + 4 * g + q) * RP + 16 * j + c] = sacc[j][q];
-  __syncthreads();
-  float *dst = part + (size_t)it.slot0 * 16 * kRpMax;
-  for (int i = threadIdx.x; i < 16 * RP; i += kThreads) {
-    const int row = i / RP, col = i - row * RP;
-    dst[row * kRpMax + col] = ((red[i] + red[16 * RP + i]) + red[32 * RP + i]) + red[48 * RP + i];
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        red[((0 * S + w) * 16 + 4 * g + q) * RP + 16 * j + c] = sacc0[j][q];
+        red[((1 * S + w) * 16 + 4 * g + q) * RP + 16 * j + c] = sacc1[j][q];
+      }
+    lds_barrier();
+    for (int b = 0; b < it.nblk; ++b) {
+      const float *rb = red + (size_t)b * S * 16 * RP;
+      float *dst = part + (size_t)(it.slot0 + b) * 16 * kRpMax;
+      for (int i = threadIdx.x; i < 16 * RP; i += kThreads) {
+        const int row = i / RP, col = i - row * RP;
+        dst[row * kRpMax + col] =
+            ((rb[i] + rb[16 * RP + i]) + rb[32 * RP + i]) + rb[48 * RP + i];
+      }
+    }
   }
 }
 
@@ -556,12 +649,12 @@ hipError_t set_lds(KernT kern, size_t bytes) {
 }  // namespace
 
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
-                          const float *gout, const float *scale_all, uint4 *bop) {
+                          const float *gout, const float *scale_all, uint4 *bop, int *counter) {
   if (ngd <= 0) return hipSuccess;
   const int RP = 16 * L.nt;
 #define FK_STAGE(DT)                                                                        \
   hipLaunchKernelGGL(stage_b_kernel<DT>, dim3(ngd), dim3(kThreads), 0, L.stream, d_gd, pdf, \
-                     gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop)
+                     gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop, counter)
   FK_DISPATCH_DT(FK_STAGE);
 #undef FK_STAGE
   return hipGetLastError();
@@ -569,17 +662,19 @@ hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, c
 
 hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, const float *pdf, int nx,
-                          int lds_units, float *part) {
+                          int lds_units, float *part, int *counter, int grid) {
   if (nitems <= 0) return hipSuccess;
-  const size_t lds = std::max((size_t)lds_units * 16, (size_t)4 * 16 * 16 * L.nt * 4);
+  // B operand, or the combine buffer [2 blocks][4 waves][16][RP] floats
+  const size_t lds = std::max((size_t)lds_units * 16, (size_t)2 * kWaves * 16 * 16 * L.nt * 4);
+  grid = std::max(1, std::min(grid, nitems));
   hipError_t err = hipSuccess;
 #define FK_HF(NT)                                                                            \
   {                                                                                          \
     auto k = had_fwd_kernel<DTV, NT>;                                                        \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                   \
-    hipLaunchKernelGGL(k, dim3(nitems), dim3(kThreads), lds, L.stream, items, segs, gd,      \
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, L.stream, items, nitems, segs, gd, \
                        (const u32x4 *)bop, pdf, L.R, L.c0, L.ncols, nx, part,                \
-                       (const u32x4 *)L.zero_page);                                          \
+                       (const u32x4 *)L.zero_page, counter);                                 \
   }
 #define FK_HF_DT(DT)           \
   {                            \

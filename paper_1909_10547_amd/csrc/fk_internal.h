@@ -60,13 +60,13 @@ struct SegRef {
   int32_t KE;
 };
 
-// Forward work item.  Hadronic: one 16-datapoint block, groups
+// Forward work item.  Hadronic: up to two 16-datapoint blocks, groups
 // [seg0, seg1) of one table, waves split the x index alpha.  DIS: up to
 // kWaves consecutive blocks (one per wave), groups [seg0, seg1).
 struct FwdItem {
   int32_t seg0, seg1;
   int32_t block0;   // first block of the item within the table
-  int32_t nblk;     // DIS: blocks in the item (<= kWaves); hadronic: 1
+  int32_t nblk;     // blocks in the item (DIS <= kWaves, hadronic <= 2)
   int32_t ndata;    // datapoints of the table
   int32_t slot0;    // first partial slot (16 x RP floats each)
 };
@@ -112,10 +112,10 @@ struct ConvLaunch {
 constexpr int kZeroPageBytes = 4096;
 
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
-                          const float *gout, const float *scale_all, uint4 *bop);
+                          const float *gout, const float *scale_all, uint4 *bop, int *counter);
 hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, const float *pdf, int nx,
-                          int lds_units, float *part);
+                          int lds_units, float *part, int *counter, int grid);
 hipError_t launch_dis_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, int lds_units, float *part);
 hipError_t launch_fwd_reduce(const ConvLaunch &L, const RedBlock *blocks, int nblocks,

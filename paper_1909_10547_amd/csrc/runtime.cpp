@@ -173,7 +173,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     const int nblk = (T->N + 15) / 16;
     const int nG = (int)T->groups.size();
     std::vector<std::vector<int>> bslots(nblk);
-    const int step = had ? 1 : kWaves;
+    const int step = had ? 2 : kWaves;
     for (int b0 = 0; b0 < nblk; b0 += step) {
       const int nb = std::min(step, nblk - b0);
       int g = 0;
@@ -300,6 +300,12 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   p.d_apart = (float *)d;
   if ((st = dev_alloc(c, kZeroPageBytes, &p.d_zero, &p.allocs))) return st;
   FK_TRY_HIP(c, hipMemset(p.d_zero, 0, kZeroPageBytes));
+  if ((st = dev_alloc(c, 64, &d, &p.allocs))) return st;
+  p.d_counter = (int *)d;
+  FK_TRY_HIP(c, hipMemset(p.d_counter, 0, 64));
+  int ncu = 0;
+  FK_TRY_HIP(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  p.grid_fwd = 2 * std::max(ncu, 1);
   p.bytes = 0;
   for (auto &a : p.allocs) p.bytes += a.second;
   return FK_OK;
@@ -341,13 +347,13 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
     ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
     hipError_t e = timed(tm, FK_K_STAGE, s, [&] {
-      return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop);
+      return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, p.d_counter);
     });
     if (e != hipSuccess) return e;
     if (p.kind == FK_HAD)
       e = timed(tm, FK_K_HAD_FWD, s, [&] {
         return launch_had_fwd(L, p.d_fitems, p.nfitems, p.d_seg, p.d_gd, p.d_bop, pdf, p.X,
-                              4 * p.maxT_fwd * RP, p.d_fpart);
+                              4 * p.maxT_fwd * RP, p.d_fpart, p.d_counter, p.grid_fwd);
       });
     else
       e = timed(tm, FK_K_DIS_FWD, s, [&] {
@@ -373,7 +379,7 @@ hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int 
     hipError_t e;
     if (p.kind == FK_HAD) {
       e = timed(tm, FK_K_STAGE, s, [&] {
-        return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop);
+        return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, nullptr);
       });
       if (e != hipSuccess) return e;
       e = timed(tm, FK_K_HAD_ADJ, s, [&] {
@@ -383,7 +389,7 @@ hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int 
     } else {
       e = timed(tm, FK_K_STAGE, s, [&] {
         return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.ngd_adj, nullptr, gout, p.d_scale,
-                              p.d_bop);
+                              p.d_bop, nullptr);
       });
       if (e != hipSuccess) return e;
       e = timed(tm, FK_K_DIS_ADJ, s, [&] {

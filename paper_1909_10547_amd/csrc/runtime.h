@@ -60,6 +60,8 @@ struct Plan {
   uint4 *d_bop = nullptr;
   float *d_fpart = nullptr, *d_apart = nullptr;
   void *d_zero = nullptr;  // kZeroPageBytes of zeros read by lanes outside a tile
+  int *d_counter = nullptr;  // work counter of the persistent forward kernel
+  int grid_fwd = 512;        // persistent workgroups (2 per compute unit)
   int maxT_fwd = 1, maxT_adj = 1;
   // bookkeeping
   std::vector<std::pair<void *, size_t>> allocs;
