@@ -105,7 +105,12 @@ fk_status fk_memory(const fk_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_by
  *              datapoint row is scaled by a power of two s_i so its largest
  *              entry fits the format; the scale is applied exactly afterwards.
  * The table is packed on the host (only active blocks, per-datapoint scale,
- * round-to-nearest-even) and copied to the device once. */
+ * round-to-nearest-even) and copied to the device once.  The device keeps
+ * two copies of each table: DIS, the table and its transpose (for the
+ * adjoint); hadronic, the symmetric part S = FK + FK^T over unordered flavour
+ * pairs (blocks b > a, and S_aa / 2 on the diagonal) for the forward, since
+ * Eq. (1) only sees S, and S over the whole symmetric pattern for the
+ * adjoint. */
 fk_status fk_load_table(fk_ctx *ctx, int32_t kind, int32_t ndata, int32_t nflav,
                         int32_t nx, const double *xgrid, const uint8_t *mask,
                         const double *fk, int32_t store_dtype, fk_table *out);

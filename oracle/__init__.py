@@ -283,10 +283,27 @@ def dis_quantized(mask, fk, pdf, fmt: str) -> np.ndarray:
     return s[:, None] * dis(mask, fq, quantize(pdf, fmt))
 
 
+def had_stored_upper(mask, fk, fmt: str):
+    """The symmetric part over unordered flavour pairs: (U, s [N], Uhat) with
+    U the blocks (a, b) of Ps with a <= b, Uhat = Q(S'_i / s_i), S'_ab = S_ab
+    for a < b and S'_aa = S_aa / 2, and s_i the scale of the full S_i.
+    Eq. (1) equals sum over a <= b of f_a S'_ab f_b."""
+    ms, S = symmetric_part(mask, fk)
+    s = datapoint_scale(np.abs(S).reshape(S.shape[0], -1).max(axis=1, initial=0.0), fmt)
+    sa, sb = np.nonzero(ms)
+    keep = sa <= sb
+    U = S[:, keep] / s[:, None, None, None]
+    U[:, (sa == sb)[keep]] *= 0.5
+    mu = np.zeros_like(ms)
+    mu[sa[keep], sb[keep]] = 1
+    return mu, s, quantize(U, fmt)
+
+
 def had_quantized(mask, fk, pdf, fmt: str) -> np.ndarray:
-    """sigma = (s/2) sum_p f_p sum_q Shat[p,q] Q(f_q) in FP64, f_p in FP32."""
-    ms, s, Sq = had_stored(mask, fk, fmt)
-    return 0.5 * s[:, None] * had_bilinear(ms, Sq, quantize(pdf, "f32"), quantize(pdf, fmt))
+    """sigma = s sum_{a<=b} f_a Uhat[a,b] Q(f_b) in FP64, f_a in FP32 (the
+    forward's stored form, had_stored_upper)."""
+    mu, s, Uq = had_stored_upper(mask, fk, fmt)
+    return s[:, None] * had_bilinear(mu, Uq, quantize(pdf, "f32"), quantize(pdf, fmt))
 
 
 def dis_grad_quantized(mask, fk, gbar, fmt: str) -> np.ndarray:

@@ -29,7 +29,7 @@ constexpr int kTMax = kUnitsMax / 4;       // k-steps per tile
 constexpr int kMaxSeg = 40;                // segments per group descriptor
 constexpr int kMaxNx = 128;                // grid points supported
 constexpr int kDisChunkUnits = kUnitsMax;  // datapoint units per DIS adjoint chunk
-constexpr int kItemUnits = 96;             // forward work per item (units per row)
+constexpr int kItemUnits = 48;             // forward work per item (units per row)
 
 inline int elems_per_unit(int dtype) {
   return dtype == FK_F32 ? 4 : (dtype == FK_BF16 ? 8 : 16);

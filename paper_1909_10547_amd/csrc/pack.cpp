@@ -273,6 +273,7 @@ void pack_had(const double *fk, const uint8_t *mask, int N, int F, int X, int dt
       if (mask[a * F + b]) pidx[a * F + b] = np++;
   pt.npairs = np;
   const size_t blk = (size_t)X * X;
+  auto in_sym = [&](int a, int b) { return pidx[a * F + b] >= 0 || pidx[b * F + a] >= 0; };
   // entry of the symmetric part S = FK + FK^T of datapoint i
   auto sval = [&](int i, int a, int b, int al, int be) -> double {
     double v = 0.0;
@@ -281,65 +282,81 @@ void pack_had(const double *fk, const uint8_t *mask, int N, int F, int X, int dt
     if (q >= 0) v += fk[((size_t)i * np + q) * blk + (size_t)be * X + al];
     return v;
   };
-  // symmetric pattern and its row groups
-  std::vector<GroupPlan> groups;
-  for (int a = 0; a < F; ++a) {
-    std::vector<std::pair<int, int>> blocks;
-    for (int b = 0; b < F; ++b)
-      if (pidx[a * F + b] >= 0 || pidx[b * F + a] >= 0) blocks.push_back({b * X, X});
-    auto g = split_groups(a, blocks, E, X);
-    groups.insert(groups.end(), g.begin(), g.end());
-  }
-  pt.groups = groups;
-  // per-datapoint scale from max |S_i|
+  // Row groups.  The forward sums Eq. (1) over unordered flavour pairs: row
+  // flavour a takes the partners b >= a, with S_ab for b > a and S_aa / 2 on
+  // the diagonal (an exact halving), so every product f_a f_b of the
+  // bilinear form is stored once.  The adjoint needs S f over the whole
+  // symmetric pattern, so it gets the full rows.
+  auto row_groups = [&](bool upper) {
+    std::vector<GroupPlan> out;
+    for (int a = 0; a < F; ++a) {
+      std::vector<std::pair<int, int>> blocks;
+      for (int b = upper ? a : 0; b < F; ++b)
+        if (in_sym(a, b)) blocks.push_back({b * X, X});
+      auto g = split_groups(a, blocks, E, X);
+      out.insert(out.end(), g.begin(), g.end());
+    }
+    return out;
+  };
+  pt.groups = row_groups(true);
+  pt.agroups = row_groups(false);
+  // per-datapoint scale from max |S_i| (shared by both copies)
   pt.scale.assign(N, 1.0f);
   parallel_for(N, [&](int i) {
     double m = 0;
     for (int a = 0; a < F; ++a)
       for (int b = a; b < F; ++b) {
-        if (pidx[a * F + b] < 0 && pidx[b * F + a] < 0) continue;
+        if (!in_sym(a, b)) continue;
         for (int al = 0; al < X; ++al)
           for (int be = 0; be < X; ++be) m = std::max(m, std::fabs(sval(i, a, b, al, be)));
       }
     pt.scale[i] = (float)datapoint_scale(m, qmax);
   });
-  size_t units = 0;
-  for (auto &g : pt.groups) {
-    g.base = units;
-    units += (size_t)N * X * g.KE;
-  }
-  pt.fk.assign(units * 16, 0);
   const int nblk = (N + 15) / 16;
-  for (auto &g : pt.groups) {
-    std::vector<int> kb(g.K), kx(g.K);
-    {
-      int k = 0;
-      for (size_t s = 0; s < g.seg_row.size(); ++s)
-        for (int t = 0; t < g.seg_len[s]; ++t, ++k) {
-          const int row = g.seg_row[s] + t;
-          kb[k] = row / X;
-          kx[k] = row % X;
-        }
+  auto pack_groups = [&](std::vector<GroupPlan> &groups, std::vector<uint8_t> &buf, bool upper) {
+    size_t units = 0;
+    for (auto &g : groups) {
+      g.base = units;
+      units += (size_t)N * X * g.KE;
     }
-    parallel_for(nblk, [&](int bl) {
-      const int nv = std::min(16, N - 16 * bl);
-      uint8_t *bbase = pt.fk.data() + (g.base + (size_t)bl * X * g.KE * 16) * 16;
-      for (int al = 0; al < X; ++al) {
-        uint8_t *abase = bbase + (size_t)al * g.KE * nv * 16;
-        for (int u = 0; u < g.KE; ++u)
-          for (int r = 0; r < nv; ++r) {
-            const int i = 16 * bl + r;
-            const double inv = 1.0 / pt.scale[i];
-            uint8_t *unit = abase + ((size_t)u * nv + r) * 16;
-            for (int e = 0; e < E; ++e) {
-              const int k = u * E + e;
-              const double v = k < g.K ? sval(i, g.a, kb[k], al, kx[k]) * inv : 0.0;
-              store_elem(unit, e, dtype, v);
-            }
+    buf.assign(units * 16, 0);
+    for (auto &g : groups) {
+      std::vector<int> kb(g.K), kx(g.K);
+      {
+        int k = 0;
+        for (size_t s = 0; s < g.seg_row.size(); ++s)
+          for (int t = 0; t < g.seg_len[s]; ++t, ++k) {
+            const int row = g.seg_row[s] + t;
+            kb[k] = row / X;
+            kx[k] = row % X;
           }
       }
-    });
-  }
+      parallel_for(nblk, [&](int bl) {
+        const int nv = std::min(16, N - 16 * bl);
+        uint8_t *bbase = buf.data() + (g.base + (size_t)bl * X * g.KE * 16) * 16;
+        for (int al = 0; al < X; ++al) {
+          uint8_t *abase = bbase + (size_t)al * g.KE * nv * 16;
+          for (int u = 0; u < g.KE; ++u)
+            for (int r = 0; r < nv; ++r) {
+              const int i = 16 * bl + r;
+              const double inv = 1.0 / pt.scale[i];
+              uint8_t *unit = abase + ((size_t)u * nv + r) * 16;
+              for (int e = 0; e < E; ++e) {
+                const int k = u * E + e;
+                double v = 0.0;
+                if (k < g.K) {
+                  v = sval(i, g.a, kb[k], al, kx[k]) * inv;
+                  if (upper && kb[k] == g.a) v *= 0.5;
+                }
+                store_elem(unit, e, dtype, v);
+              }
+            }
+        }
+      });
+    }
+  };
+  pack_groups(pt.groups, pt.fk, true);
+  pack_groups(pt.agroups, pt.fkT, false);
 }
 
 }  // namespace fk

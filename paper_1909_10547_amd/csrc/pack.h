@@ -24,10 +24,11 @@ struct TChunk {
 };
 
 struct PackedTable {
-  std::vector<GroupPlan> groups;
+  std::vector<GroupPlan> groups;   // forward row groups
+  std::vector<GroupPlan> agroups;  // hadronic only: adjoint row groups (into fkT)
   std::vector<float> scale;   // s_i, powers of two
   std::vector<uint8_t> fk;    // packed forward units (16 bytes each)
-  std::vector<uint8_t> fkT;   // DIS only: transposed units
+  std::vector<uint8_t> fkT;   // DIS: transposed units; hadronic: full symmetric part
   std::vector<TChunk> tchunks;
   std::vector<int> active;    // DIS: active flavours
   int nact = 0, npairs = 0;

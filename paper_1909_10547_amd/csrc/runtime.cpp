@@ -148,7 +148,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
       p.maxT_fwd = std::max(p.maxT_fwd, (g.KE + 3) / 4);
     }
   p.ngd_fwd = (int)gd.size();
-  std::vector<std::vector<int>> chunkgd(ts.size());
+  std::vector<std::vector<int>> chunkgd(ts.size()), asegidx(ts.size());
   if (!had)
     for (size_t t = 0; t < ts.size(); ++t)
       for (auto &ch : ts[t]->tchunks) {
@@ -156,7 +156,14 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
         p.maxT_adj = std::max(p.maxT_adj, (ch.KE + 3) / 4);
       }
   else
-    p.maxT_adj = p.maxT_fwd;
+    // the hadronic adjoint runs over the full symmetric rows (second copy)
+    for (size_t t = 0; t < ts.size(); ++t)
+      for (auto &g : ts[t]->agroups) {
+        const int gi = add_gd(g.a, 0, g.seg_row, g.seg_len, g.K, g.KE);
+        segs.push_back({(const uint4 *)((const char *)ts[t]->d_fkT + g.base * 16), gi, g.KE});
+        asegidx[t].push_back((int)segs.size() - 1);
+        p.maxT_adj = std::max(p.maxT_adj, (g.KE + 3) / 4);
+      }
   p.ngd_adj = (int)gd.size() - p.ngd_fwd;
 
   // ---- forward items.  An item runs consecutive groups of one block (DIS:
@@ -207,6 +214,24 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     }
   }
 
+  // Hand the forward items out longest first (the persistent kernel takes
+  // them in list order), so the last ones to finish are short.  Each item
+  // keeps its partial slots, so the order does not change any result.
+  {
+    std::vector<double> cost(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+      double c = 0;
+      for (int sg = items[k].seg0; sg < items[k].seg1; ++sg) c += segs[sg].KE + 4.0;
+      cost[k] = c * items[k].nblk;
+    }
+    std::vector<size_t> order(items.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<FwdItem> sorted(items.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
+    items.swap(sorted);
+  }
+
   // ---- adjoint items and the CSR of partial rows per output row (a, x)
   std::vector<std::vector<int64_t>> rows_out((size_t)F * X);
   std::vector<HadAdjItem> hadj;
@@ -214,22 +239,22 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   size_t apart_floats = 0;
   if (had) {
     double pairs = 0;
-    for (auto *t : ts) pairs += (double)t->groups.size() * ((t->N + 15) / 16);
+    for (auto *t : ts) pairs += (double)t->agroups.size() * ((t->N + 15) / 16);
     const int tb = std::max(1, (int)std::lround(pairs / 768.0));
     int slot = 0;
     for (size_t t = 0; t < ts.size(); ++t) {
       const Table *T = ts[t];
       const int nblk = (T->N + 15) / 16;
-      for (size_t gi = 0; gi < T->groups.size(); ++gi)
+      for (size_t gi = 0; gi < T->agroups.size(); ++gi)
         for (int b0 = 0; b0 < nblk; b0 += tb) {
           HadAdjItem it;
-          it.seg = segidx[t][gi];
+          it.seg = asegidx[t][gi];
           it.block0 = b0;
           it.block1 = std::min(nblk, b0 + tb);
           it.ndata = T->N;
           it.wrow0 = p.row0[t];
           it.slot = slot;
-          const int a = T->groups[gi].a;
+          const int a = T->agroups[gi].a;
           for (int al = 0; al < X; ++al)
             rows_out[(size_t)a * X + al].push_back((int64_t)slot * X * kRpMax + (int64_t)al * kRpMax);
           ++slot;
@@ -363,7 +388,7 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
     if (e != hipSuccess) return e;
     e = timed(tm, FK_K_FWD_REDUCE, s, [&] {
       return launch_fwd_reduce(L, p.d_rblocks, p.nrblocks, p.d_slot_idx, p.d_fpart, p.d_scale,
-                               p.kind == FK_HAD ? 0.5f : 1.0f, out);
+                               1.0f, out);
     });
     if (e != hipSuccess) return e;
   }
@@ -379,7 +404,8 @@ hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int 
     hipError_t e;
     if (p.kind == FK_HAD) {
       e = timed(tm, FK_K_STAGE, s, [&] {
-        return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, nullptr);
+        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.ngd_adj, pdf, nullptr, p.d_scale, p.d_bop,
+                              nullptr);
       });
       if (e != hipSuccess) return e;
       e = timed(tm, FK_K_HAD_ADJ, s, [&] {
@@ -516,6 +542,7 @@ fk_status fk_load_table(fk_ctx *ctx, int32_t kind, int32_t ndata, int32_t nflav,
     return set_err(ctx, FK_E_HIP, "fk_load_table: copy to device: %s", hipGetErrorString(e));
   }
   t->groups = std::move(pt.groups);
+  t->agroups = std::move(pt.agroups);
   t->tchunks = std::move(pt.tchunks);
   t->active = std::move(pt.active);
   t->scale = std::move(pt.scale);

@@ -21,8 +21,9 @@ namespace fk {
 struct Table {
   int kind = 0, N = 0, F = 0, X = 0, dtype = 0;
   std::vector<double> xgrid;
-  std::vector<GroupPlan> groups;
-  std::vector<TChunk> tchunks;
+  std::vector<GroupPlan> groups;   // forward row groups (into d_fk)
+  std::vector<GroupPlan> agroups;  // hadronic adjoint row groups (into d_fkT)
+  std::vector<TChunk> tchunks;     // DIS adjoint chunks (into d_fkT)
   std::vector<int> active;
   std::vector<float> scale;
   int nact = 0;

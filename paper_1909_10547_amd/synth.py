@@ -285,7 +285,7 @@ class Workload:
             yield self.table(d)
 
 
-def config0() -> Workload:
+def dis_single_workload() -> Workload:
     """One DIS dataset, N=100, 14 flavours (9 active), 30 log-spaced points
     in [1e-5, 0.9], one replica, seed 0."""
     return Workload(name="dis_cpu_n100_x30_r1", seed=0,
@@ -293,7 +293,7 @@ def config0() -> Workload:
                     ndata=[100], nrep=1, jitter=0.0, kinds=["dis"])
 
 
-def config1(scale: float = 1.0) -> Workload:
+def dis_fit_workload(scale: float = 1.0) -> Workload:
     """20 DIS datasets, N ~ U{50..600}, X=50 in [1e-7, 1], 9 active
     flavours each, R=100 jittered replicas, seed 1.  ``scale`` shrinks N
     for CPU-sized tests."""
@@ -305,7 +305,7 @@ def config1(scale: float = 1.0) -> Workload:
                     ndata=n, nrep=100, kinds=["dis"] * 20)
 
 
-def config2(scale: float = 1.0) -> Workload:
+def had_fit_workload(scale: float = 1.0) -> Workload:
     """10 hadronic datasets, N ~ U{20..1000}, 60 active ordered flavour
     pairs from a random symmetric mask, X=50 in [1e-7, 1], symmetric FK,
     R=100 jittered replicas, seed 2."""
@@ -319,7 +319,7 @@ def config2(scale: float = 1.0) -> Workload:
 
 @dataclass
 class FitWorkload:
-    """Datasets of configs 1 and 2 with a covariance per dataset (seed 3)."""
+    """Datasets of the DIS and hadronic fit workloads with a covariance per dataset (seed 3)."""
     dis: Workload
     had: Workload
     seed: int = 3
@@ -351,8 +351,8 @@ class FitWorkload:
         return [c for c, _ in out], [d for _, d in out]
 
 
-def config3(scale: float = 1.0) -> FitWorkload:
-    return FitWorkload(dis=config1(scale), had=config2(scale))
+def global_fit_workload(scale: float = 1.0) -> FitWorkload:
+    return FitWorkload(dis=dis_fit_workload(scale), had=had_fit_workload(scale))
 
 
 @dataclass
@@ -365,7 +365,7 @@ class ServingWorkload:
     rep_choices: tuple = (1, 4, 16, 100)
 
     def catalogue(self):
-        """Yields ("dis"|"had", table).  cfg1's 20 DIS, cfg2's 10 hadronic,
+        """Yields ("dis"|"had", table).  dis_fit's 20 DIS, had_fit's 10 hadronic,
         then 2 DIS and 2 hadronic tables with N = big_n."""
         for t in self.dis.tables():
             yield "dis", t
@@ -395,8 +395,8 @@ class ServingWorkload:
         return sample_pdf(prm, self.dis.xgrid, nrep, 0.05 if nrep > 1 else 0.0, rng)
 
 
-def config4(scale: float = 1.0, big_n: int = 2000) -> ServingWorkload:
-    return ServingWorkload(dis=config1(scale), had=config2(scale), big_n=big_n)
+def serving_workload(scale: float = 1.0, big_n: int = 2000) -> ServingWorkload:
+    return ServingWorkload(dis=dis_fit_workload(scale), had=had_fit_workload(scale), big_n=big_n)
 
 
 # ---------------------------------------------------------------------------

@@ -82,19 +82,19 @@ def check_grad(c, kind, tab, pdf, gbar, fmt, label):
 @pytest.mark.parametrize("R", [1, 100, 130])
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
 def test_dis_adjoint(ctx, R, fmt):
-    w = synth.config1(scale=0.2)
+    w = synth.dis_fit_workload(scale=0.2)
     tab = w.table(4)
     rng = np.random.default_rng(R)
-    check_grad(ctx, "dis", tab, w.pdf(R), rng.normal(size=(tab.ndata, R)), fmt, "config1-d4")
+    check_grad(ctx, "dis", tab, w.pdf(R), rng.normal(size=(tab.ndata, R)), fmt, "dis_fit-d4")
 
 
 @pytest.mark.parametrize("R", [1, 100, 130])
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
 def test_had_adjoint(ctx, R, fmt):
-    w = synth.config2(scale=0.05)
+    w = synth.had_fit_workload(scale=0.05)
     tab = w.table(3)
     rng = np.random.default_rng(R)
-    check_grad(ctx, "had", tab, w.pdf(R), rng.normal(size=(tab.ndata, R)), fmt, "config2-d3")
+    check_grad(ctx, "had", tab, w.pdf(R), rng.normal(size=(tab.ndata, R)), fmt, "had_fit-d3")
 
 
 def test_had_adjoint_general_table(ctx):
@@ -107,7 +107,7 @@ def test_had_adjoint_general_table(ctx):
 
 
 def test_accumulate_and_groups(ctx):
-    w = synth.config2(scale=0.03)
+    w = synth.had_fit_workload(scale=0.03)
     tabs = [w.table(d) for d in range(3)]
     pdf32 = f32(w.pdf(16))
     rng = np.random.default_rng(3)
@@ -129,7 +129,7 @@ def test_accumulate_and_groups(ctx):
     for h in hs:
         fkconv.fk_unload_table(ctx.ctx, h)
     # DIS group
-    w1 = synth.config1(scale=0.1)
+    w1 = synth.dis_fit_workload(scale=0.1)
     dt = [w1.table(d) for d in range(5)]
     hs = [ctx.load(t, "f32") for t in dt]
     grp = fkconv.fk_group_create(ctx.ctx, hs)
@@ -153,7 +153,7 @@ def test_central_differences_of_the_gpu_forward(ctx):
     # L(f) = sum gbar * sigma(f) is quadratic in f, so the central difference
     # along any direction v equals <grad L, v> exactly; a large step keeps the
     # FP32 rounding noise of the forward small.
-    w = synth.config2(scale=0.04)
+    w = synth.had_fit_workload(scale=0.04)
     tab = w.table(5)
     pdf32 = f32(w.pdf(8))
     rng = np.random.default_rng(11)

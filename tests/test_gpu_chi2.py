@@ -63,8 +63,8 @@ def test_not_positive_definite(ctx):
 
 
 def test_fit_gradient_against_oracle(ctx):
-    # datasets of configs 1 and 2 (reduced sizes), covariance per dataset
-    w = synth.config3(scale=0.04)
+    # datasets of the DIS and hadronic fit workloads (reduced sizes), covariance per dataset
+    w = synth.global_fit_workload(scale=0.04)
     dis_t = [w.dis.table(d) for d in range(4)]
     had_t = [w.had.table(d) for d in range(3)]
     R = 6

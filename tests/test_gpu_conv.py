@@ -87,35 +87,35 @@ def check(kind, tab, pdf, c, fmt, label):
 # ---------------------------------------------------------------------------
 
 def test_dis_config0_all_formats(ctx):
-    w = synth.config0()
+    w = synth.dis_single_workload()
     tab = w.table(0)
     pdf = w.pdf()
     for fmt in ("f32", "bf16", "e4m3"):
-        check("dis", tab, pdf, ctx, fmt, "config0")
+        check("dis", tab, pdf, ctx, fmt, "dis_single")
 
 
 @pytest.mark.parametrize("R", [1, 4, 16, 100, 130])
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
 def test_dis_replica_counts(ctx, R, fmt):
-    w = synth.config1(scale=0.1)
+    w = synth.dis_fit_workload(scale=0.1)
     tab = w.table(2)
     pdf = w.pdf(R)
-    check("dis", tab, pdf, ctx, fmt, "config1-d2")
+    check("dis", tab, pdf, ctx, fmt, "dis_fit-d2")
 
 
 @pytest.mark.parametrize("R", [1, 4, 16, 100, 130])
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
 def test_had_replica_counts(ctx, R, fmt):
-    w = synth.config2(scale=0.05)
+    w = synth.had_fit_workload(scale=0.05)
     tab = w.table(1)
     pdf = w.pdf(R)
-    check("had", tab, pdf, ctx, fmt, "config2-d1")
+    check("had", tab, pdf, ctx, fmt, "had_fit-d1")
 
 
 def test_had_fp8_against_stored_operand(ctx):
-    w = synth.config2(scale=0.03)
+    w = synth.had_fit_workload(scale=0.03)
     tab = w.table(0)
-    check("had", tab, w.pdf(16), ctx, "e4m3", "config2-d0")
+    check("had", tab, w.pdf(16), ctx, "e4m3", "had_fit-d0")
 
 
 @pytest.mark.parametrize("fmt", ["f32", "bf16", "e4m3"])
@@ -171,7 +171,7 @@ def test_edge_shapes(ctx, shape):
 
 
 def test_groups_concatenate_datasets(ctx):
-    w = synth.config2(scale=0.03)
+    w = synth.had_fit_workload(scale=0.03)
     tabs = [w.table(d) for d in range(4)]
     pdf32 = f32(w.pdf(100))
     for fmt in ("f32", "bf16"):
@@ -197,7 +197,7 @@ def test_groups_concatenate_datasets(ctx):
 
 
 def test_deterministic(ctx):
-    w = synth.config2(scale=0.05)
+    w = synth.had_fit_workload(scale=0.05)
     tab = w.table(2)
     pdf = dev(f32(w.pdf(100)))
     h = ctx.load(tab, "bf16")
@@ -208,7 +208,7 @@ def test_deterministic(ctx):
 
 
 def test_error_paths(ctx):
-    w = synth.config0()
+    w = synth.dis_single_workload()
     tab = w.table(0)
     h = ctx.load(tab, "f32")
     pdf = dev(f32(w.pdf()))
@@ -225,7 +225,7 @@ def test_error_paths(ctx):
     assert e.value.code == fkconv.FK_E_HANDLE
     small = fkconv.Context(0, hbm_budget_bytes=64 << 10)
     with pytest.raises(fkconv.FKError) as e:
-        small.load(synth.config2(scale=0.05).table(0), "f32")
+        small.load(synth.had_fit_workload(scale=0.05).table(0), "f32")
     assert e.value.code == fkconv.FK_E_BUDGET
     assert fkconv.fk_memory(small.ctx)[0] == 0
     small.close()

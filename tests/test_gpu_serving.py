@@ -22,8 +22,8 @@ def say(*a):
 
 
 def test_mixed_requests_equal_alone_runs():
-    wd = synth.config1(scale=0.15)
-    wh = synth.config2(scale=0.04)
+    wd = synth.dis_fit_workload(scale=0.15)
+    wh = synth.had_fit_workload(scale=0.04)
     cat = [("dis", wd.table(0)), ("dis", wd.table(1)), ("had", wh.table(0)), ("had", wh.table(1)),
            ("had", wh.table(2))]
     rng = np.random.default_rng(4)
@@ -86,7 +86,7 @@ def test_mixed_requests_equal_alone_runs():
 
 
 def test_serving_errors():
-    w = synth.config1(scale=0.1)
+    w = synth.dis_fit_workload(scale=0.1)
     t = w.table(0)
     with fkconv.Context(0) as c:
         h = c.load(t, "bf16")

@@ -5,18 +5,18 @@ from paper_1909_10547_amd import synth
 
 
 def test_config_sizes_and_determinism():
-    c1, c2 = synth.config1(), synth.config2()
+    c1, c2 = synth.dis_fit_workload(), synth.had_fit_workload()
     assert len(c1.ndata) == 20 and all(50 <= n <= 600 for n in c1.ndata)
     assert len(c2.ndata) == 10 and all(20 <= n <= 1000 for n in c2.ndata)
-    assert synth.config1().ndata == c1.ndata
-    c0 = synth.config0()
+    assert synth.dis_fit_workload().ndata == c1.ndata
+    c0 = synth.dis_single_workload()
     assert c0.ndata == [100] and c0.xgrid.shape == (30,) and c0.nrep == 1
     assert np.isclose(c0.xgrid[0], 1e-5) and np.isclose(c0.xgrid[-1], 0.9)
     assert np.isclose(c1.xgrid[0], 1e-7) and c1.xgrid[-1] == 1.0
 
 
 def test_dis_masks_and_values():
-    w = synth.config1(scale=0.05)
+    w = synth.dis_fit_workload(scale=0.05)
     t0 = w.table(3)
     t1 = w.table(3)
     np.testing.assert_array_equal(t0.fk, t1.fk)
@@ -24,7 +24,7 @@ def test_dis_masks_and_values():
 
 
 def test_had_masks_symmetry_and_counts():
-    w = synth.config2(scale=0.02)
+    w = synth.had_fit_workload(scale=0.02)
     t = w.table(0)
     assert int(t.mask.sum()) == 60
     assert int(np.trace(t.mask)) == 4
@@ -36,7 +36,7 @@ def test_had_masks_symmetry_and_counts():
 
 
 def test_pdf_replicas():
-    w = synth.config1(scale=0.05)
+    w = synth.dis_fit_workload(scale=0.05)
     f = w.pdf()
     assert f.shape == (14, 50, 100)
     assert np.all(np.isfinite(f))
