@@ -197,47 +197,47 @@ __device__ __forceinline__ u32x4 pack_unit<FK_FP8E4M3>(const float *v) {
 // ---------------------------------------------------------------------------
 template <int DT>
 __global__ void __launch_bounds__(kThreads)
-    stage_b_kernel(const GroupDesc *__restrict__ gd, const float *__restrict__ pdf,
+    stage_b_kernel(const GroupDesc *__restrict__ gd, int ngd, const float *__restrict__ pdf,
                    const float *__restrict__ gout, const float *__restrict__ scale_all, int R,
-                   int c0, int ncols, int RP, u32x4 *__restrict__ bop, int *counter) {
+                   int c0, int ncols, int RP, u32x4 *__restrict__ bop, int *counter,
+                   float *__restrict__ fstage, int nx) {
   constexpr int E = Mma<DT>::E;
   // the forward kernel that follows on the stream takes items from *counter
-  if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
-  __shared__ int s_row[kMaxSeg], s_start[kMaxSeg + 1];
-  const GroupDesc *G = gd + blockIdx.x;
-  const int nseg = G->nseg, K = G->K, src_kind = G->src;
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int s = 0; s < nseg; ++s) {
-      s_row[s] = G->seg_row[s];
-      s_start[s] = acc;
-      acc += G->seg_len[s];
-    }
-    s_start[nseg] = acc;
+  if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;
+  // grid: x = chunk of kThreads units (or floats), y = descriptor
+  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if ((int)blockIdx.y >= ngd) {
+    // rows past the descriptors: FP32 PDF rows of flavour a for the
+    // epilogue of the stream kernel, [alpha][RP], zero for columns >= ncols
+    const int a = blockIdx.y - ngd;
+    if (idx >= nx * RP) return;
+    const int al = idx / RP, n = idx - al * RP;
+    fstage[(size_t)a * nx * RP + idx] = n < ncols ? pdf[((size_t)a * nx + al) * R + c0 + n] : 0.f;
+    return;
   }
-  __syncthreads();
-  const float *src = src_kind == 0 ? pdf : gout;
+  const GroupDesc *G = gd + blockIdx.y;
   const int KEpad = ((G->KE + 3) >> 2) << 2;
-  const int units = KEpad * RP;
-  u32x4 *dst = bop + G->bop_off;
-  for (int idx = threadIdx.x; idx < units; idx += kThreads) {
-    const int u = idx / RP, n = idx - u * RP;
-    float v[E];
-    int s = 0;
+  if (idx >= KEpad * RP) return;
+  const int nseg = G->nseg, K = G->K, src_kind = G->src;
+  const float *src = src_kind == 0 ? pdf : gout;
+  const int u = idx / RP, n = idx - u * RP;
+  // segment of the unit's first element, then walk forward
+  int s = 0, start = 0;
+  while (s < nseg - 1 && start + G->seg_len[s] <= u * E) start += G->seg_len[s++];
+  float v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = u * E + e;
-      float x = 0.f;
-      if (k < K && n < ncols) {
-        while (s_start[s + 1] <= k) ++s;
-        const int row = s_row[s] + (k - s_start[s]);
-        x = src[(size_t)row * R + c0 + n];
-        if (src_kind == 1) x *= scale_all[row];
-      }
-      v[e] = x;
+  for (int e = 0; e < E; ++e) {
+    const int k = u * E + e;
+    float x = 0.f;
+    if (k < K && n < ncols) {
+      while (start + G->seg_len[s] <= k) start += G->seg_len[s++];
+      const int row = G->seg_row[s] + (k - start);
+      x = src[(size_t)row * R + c0 + n];
+      if (src_kind == 1) x *= scale_all[row];
     }
-    dst[idx] = pack_unit<DT>(v);
+    v[e] = x;
   }
+  bop[G->bop_off + idx] = pack_unit<DT>(v);
 }
 
 // f[a][alpha][c0 + 16j + lane%16] for the epilogue; columns >= ncols (and
@@ -419,6 +419,223 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ---------------------------------------------------------------------------
+// Streaming hadronic forward.  Each workgroup walks a static list of
+// segment records (one group of one item each); the waves split alpha as in
+// had_fwd_kernel.  Seen from one wave, the FK tiles of its (group, alpha)
+// jobs form one flat stream of k-steps (T per job), and a ring of W k-steps
+// of both tiles of the pair stays in flight in registers, so the bytes in
+// flight do not depend on the group size.  Every k-step issues exactly two
+// loads, which keeps the compiler's waits on the ring exact.
+//
+// The B operand and the FP32 PDF row of the epilogue of each group go to one
+// of two LDS buffers by LDS-DMA, issued when the refill cursor enters the
+// group, W-1 k-steps before the first MFMA needs them; at every group change
+// each wave waits for its own copies (they were issued before the last
+// 2W-2 ring loads) and a workgroup barrier publishes them.  The buffer a
+// copy overwrites was released at the previous group change, provided every
+// group lasts at least W k-steps per wave (the host checks this).  At the
+// end of an item the four waves' partial sums are combined in a fixed order
+// in the buffer of the group just finished and written to the item's slots.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// One LDS-DMA instruction: lane l copies 16 bytes from ``src`` (its own
+// address) to LDS ``dst`` + 16 l (``dst`` uniform, set in M0).  Written as
+// inline assembly so that the compiler does not treat it as a pending write
+// to all of LDS: it would then wait for every load in flight (vmcnt(0))
+// before each LDS read of the other buffer.  The copies are waited for
+// explicitly (wait_vmcnt); the compiler's own waits on the ring only grow
+// stricter from loads it does not count.
+__device__ __forceinline__ void dma16(gu32x4_ptr src, u32x4 *dst) {
+  const unsigned l = (unsigned)(uintptr_t)(__attribute__((address_space(3))) void *)dst;
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+               :
+               : "s"(__builtin_amdgcn_readfirstlane(l)), "v"(src)
+               : "memory", "m0");
+}
+
+// Copy ``units`` 16-byte units from global ``src`` to LDS ``dst``:
+// instruction k moves units [64k, 64k+64); wave w issues instructions w,
+// w+4, ...  Lanes past the end read the zero page and write inside the last
+// KiB of the copy (buffers are whole KiB).
+__device__ __forceinline__ void dma_copy(u32x4 *dst, const u32x4 *src, int units,
+                                         const u32x4 *zp, int w, int lane) {
+  const int n = (units + 63) >> 6;
+  for (int k = w; k < n; k += kWaves) {
+    const int u = 64 * k + lane;
+    dma16(u < units ? as_global(src) + u : as_global(zp) + lane, dst + 64 * k);
+  }
+}
+
+template <int DT, int NT, int W>
+__global__ void __launch_bounds__(kThreads, 1)
+    had_stream_kernel(const StreamSeg *__restrict__ recs, const int32_t *__restrict__ wg_ptr,
+                      const u32x4 *__restrict__ bop, const float *__restrict__ fstage, int nx,
+                      int bufsz, float *__restrict__ part, const u32x4 *zp) {
+  constexpr int RP = 16 * NT;
+  constexpr int S = kWaves;
+  extern __shared__ u32x4 lds[];
+  // the wave index is uniform: say so, so that every cursor below lives in
+  // scalar registers and every branch on it is a scalar branch
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int r_begin = wg_ptr[blockIdx.x], r_end = wg_ptr[blockIdx.x + 1];
+  if (r_begin >= r_end) return;
+  const gu32x4_ptr zpg = as_global(zp);
+
+  u32x4 a0[W], a1[W];
+  f32x4 acc0[NT], acc1[NT], sacc0[NT], sacc1[NT];
+  zero(acc0);
+  zero(acc1);
+  zero(sacc0);
+  zero(sacc1);
+
+  // B operand and PDF row of record ``q`` into buffer ``par``
+  auto stage = [&](const StreamSeg &q, int par) {
+    u32x4 *buf = lds + par * bufsz;
+    const int ub = 4 * q.T * RP;
+    dma_copy(buf, bop + q.bop_off, ub, zp, w, lane);
+    dma_copy(buf + ub, (const u32x4 *)(fstage + (size_t)q.flav * nx * RP), nx * RP / 4, zp, w,
+             lane);
+  };
+
+  // refill cursor: record rr, job alpha r_al, k-step r_t
+  int rr = r_begin, r_al = w, r_t = 0, rpar = 0;
+  bool r_done = false;
+  StreamSeg Rq = recs[rr];
+  gu32x4_ptr pa0 = as_global(Rq.a0) + (size_t)r_al * Rq.nv0 * Rq.KE;
+  gu32x4_ptr pa1 = as_global(Rq.a1) + (size_t)r_al * Rq.nv1 * Rq.KE;
+  // Two loads per call on every path (past the end of the list, of the zero
+  // page); the cursor advance has no loads.
+  auto refill = [&](u32x4 &x0, u32x4 &x1) {
+    const int u = 4 * r_t + g;
+    const bool ok0 = !r_done && c < Rq.nv0 && u < Rq.KE;
+    const bool ok1 = !r_done && c < Rq.nv1 && u < Rq.KE;
+    // offsets inside one tile are small: 32-bit arithmetic
+    x0 = __builtin_nontemporal_load(ok0 ? pa0 + (u * Rq.nv0 + c) : zpg + lane);
+    x1 = __builtin_nontemporal_load(ok1 ? pa1 + (u * Rq.nv1 + c) : zpg + lane);
+    if (!r_done) {
+      if (++r_t == Rq.T) {
+        r_t = 0;
+        r_al += S;
+        if (r_al >= nx) {
+          r_al = w;
+          if (++rr == r_end) {
+            r_done = true;
+          } else {
+            Rq = recs[rr];
+            rpar ^= 1;
+            __builtin_amdgcn_sched_barrier(0);
+            stage(Rq, rpar);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        pa0 = as_global(Rq.a0) + (size_t)r_al * Rq.nv0 * Rq.KE;
+        pa1 = as_global(Rq.a1) + (size_t)r_al * Rq.nv1 * Rq.KE;
+      }
+    }
+  };
+
+  // the four waves' sums of the item, combined in a fixed order
+  auto flush = [&](const StreamSeg &q, int par) {
+    lds_barrier();
+    float *red = (float *)(lds + par * bufsz);  // [block][wave][16][RP]
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        red[((0 * S + w) * 16 + 4 * g + e) * RP + 16 * j + c] = sacc0[j][e];
+        red[((1 * S + w) * 16 + 4 * g + e) * RP + 16 * j + c] = sacc1[j][e];
+      }
+    lds_barrier();
+    const int nb = q.nv1 > 0 ? 2 : 1;
+    for (int b = 0; b < nb; ++b) {
+      const float *rb = red + (size_t)b * S * 16 * RP;
+      float *dst = part + (size_t)(q.slot + b) * 16 * kRpMax;
+      for (int i = threadIdx.x; i < 16 * RP; i += kThreads) {
+        const int rw = i / RP, col = i - rw * RP;
+        dst[rw * kRpMax + col] = ((rb[i] + rb[16 * RP + i]) + rb[32 * RP + i]) + rb[48 * RP + i];
+      }
+    }
+    lds_barrier();
+    zero(sacc0);
+    zero(sacc1);
+  };
+
+  // consume cursor: record cr, job alpha c_al, k-step c_t, buffer cpar
+  int cr = r_begin, c_al = w, c_t = 0, cpar = 0;
+  StreamSeg Cq = Rq;
+  bool done = false;
+  auto consume = [&](const u32x4 &x0, const u32x4 &x1) {
+    if (done) return;
+    const u32x4 *bp = lds + cpar * bufsz + (4 * c_t + g) * RP + c;
+    // all B reads of the k-step first, so their latencies overlap
+    u32x4 b[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) b[j] = bp[16 * j];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      Mma<DT>::run(x0, b[j], acc0[j]);
+      Mma<DT>::run(x1, b[j], acc1[j]);
+    }
+    if (++c_t == Cq.T) {
+      c_t = 0;
+      const float *fl = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c_al * RP + c;
+      float fv[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) fv[j] = fl[16 * j];
+      // one column tile at a time keeps few accumulators in flight
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        sacc0[j] += acc0[j] * fv[j];
+        sacc1[j] += acc1[j] * fv[j];
+        acc0[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      c_al += S;
+      if (c_al >= nx) {
+        c_al = w;
+        if (Cq.last) flush(Cq, cpar);
+        if (++cr == r_end) {
+          done = true;
+        } else {
+          Cq = recs[cr];
+          cpar ^= 1;
+          wait_vmcnt<2 * W - 2>();
+          lds_barrier();
+        }
+      }
+    }
+  };
+
+  stage(Rq, 0);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < W; ++i) refill(a0[i], a1[i]);
+  wait_vmcnt<2 * W>();
+  lds_barrier();
+  // The loop leaves only at the end of the unrolled body (steps after the
+  // last one consume nothing and refill from the zero page): an exit from
+  // inside the body would be routed through the loop latch by the control
+  // flow structurizer, and the compiler's waits at the loop head would then
+  // assume that the ring holds the loads of a single step.
+  do {
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      consume(a0[i], a1[i]);
+      refill(a0[i], a1[i]);
+    }
+  } while (!done);
+  wait_vmcnt<0>();
+}
+
+// ---------------------------------------------------------------------------
 // DIS forward: each wave owns one 16-datapoint block of the item.
 // ---------------------------------------------------------------------------
 template <int DT, int NT>
@@ -591,14 +808,25 @@ __global__ void __launch_bounds__(kThreads)
     fwd_reduce_kernel(const RedBlock *__restrict__ blocks, const int32_t *__restrict__ slot_idx,
                       const float *__restrict__ part, const float *__restrict__ scale_all,
                       float factor, int R, int c0, int ncols, float *__restrict__ out) {
-  const RedBlock b = blocks[blockIdx.x];
-  for (int i = threadIdx.x; i < b.nv * ncols; i += kThreads) {
-    const int row = i / ncols, col = i - row * ncols;
-    float acc = 0.f;
-    for (int k = b.k0; k < b.k1; ++k) acc += part[(size_t)slot_idx[k] * 16 * kRpMax + row * kRpMax + col];
-    const int orow = b.orow + row;
-    out[(size_t)orow * R + c0 + col] = factor * scale_all[orow] * acc;
+  // grid: x = chunk of kThreads outputs of the block, y = output block
+  const RedBlock b = blocks[blockIdx.y];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= b.nv * ncols) return;
+  const int row = i / ncols, col = i - row * ncols;
+  const float *p = part + row * kRpMax + col;
+  // slots in list order; the loads of eight slots are issued together
+  float acc = 0.f;
+  int k = b.k0;
+  for (; k + 8 <= b.k1; k += 8) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = p[(size_t)slot_idx[k + q] * 16 * kRpMax];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += v[q];
   }
+  for (; k < b.k1; ++k) acc += p[(size_t)slot_idx[k] * 16 * kRpMax];
+  const int orow = b.orow + row;
+  out[(size_t)orow * R + c0 + col] = factor * scale_all[orow] * acc;
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -649,12 +877,19 @@ hipError_t set_lds(KernT kern, size_t bytes) {
 }  // namespace
 
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
-                          const float *gout, const float *scale_all, uint4 *bop, int *counter) {
+                          const float *gout, const float *scale_all, uint4 *bop, int *counter,
+                          float *fstage, int nflav, int nx) {
   if (ngd <= 0) return hipSuccess;
   const int RP = 16 * L.nt;
-#define FK_STAGE(DT)                                                                        \
-  hipLaunchKernelGGL(stage_b_kernel<DT>, dim3(ngd), dim3(kThreads), 0, L.stream, d_gd, pdf, \
-                     gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop, counter)
+  const int rows = ngd + (fstage ? nflav : 0);
+  // one thread per staged unit (a group's B has at most 4*kTMax*RP units)
+  int units = 4 * kTMax * RP;
+  if (fstage) units = std::max(units, nx * RP);
+  const dim3 grid((units + kThreads - 1) / kThreads, rows);
+#define FK_STAGE(DT)                                                                          \
+  hipLaunchKernelGGL(stage_b_kernel<DT>, grid, dim3(kThreads), 0, L.stream, d_gd, ngd, pdf,   \
+                     gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop, counter, fstage,  \
+                     nx)
   FK_DISPATCH_DT(FK_STAGE);
 #undef FK_STAGE
   return hipGetLastError();
@@ -687,6 +922,41 @@ hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems,
   return hipGetLastError();
 }
 
+size_t had_stream_lds_bytes(int nt, int nx, int maxT) {
+  const int RP = 16 * nt;
+  // B operand + PDF rows, or the combine buffer [2][4][16][RP] floats
+  int units = std::max(4 * maxT * RP + nx * RP / 4, 2 * kWaves * 16 * RP / 4);
+  units = (units + 63) / 64 * 64;
+  const size_t bytes = (size_t)2 * units * 16;
+  return bytes <= 163840 ? bytes : 0;
+}
+
+hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const int32_t *wg_ptr,
+                             int grid, const uint4 *bop, const float *fstage, int nx, int maxT,
+                             float *part) {
+  if (grid <= 0) return hipSuccess;
+  const size_t lds = had_stream_lds_bytes(L.nt, nx, maxT);
+  if (!lds) return hipErrorInvalidValue;
+  const int bufsz = (int)(lds / 32);  // units per buffer
+  hipError_t err = hipSuccess;
+#define FK_HS(NT)                                                                              \
+  {                                                                                            \
+    auto k = had_stream_kernel<DTV, NT, kStreamW>;                                             \
+    if ((err = set_lds(k, lds)) != hipSuccess) return err;                                     \
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, L.stream, recs, wg_ptr,             \
+                       (const u32x4 *)bop, fstage, nx, bufsz, part, (const u32x4 *)L.zero_page); \
+  }
+#define FK_HS_DT(DT)           \
+  {                            \
+    constexpr int DTV = DT;    \
+    FK_DISPATCH_NT(FK_HS);     \
+  }
+  FK_DISPATCH_DT(FK_HS_DT);
+#undef FK_HS
+#undef FK_HS_DT
+  return hipGetLastError();
+}
+
 hipError_t launch_dis_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, int lds_units, float *part) {
   if (nitems <= 0) return hipSuccess;
@@ -714,7 +984,8 @@ hipError_t launch_fwd_reduce(const ConvLaunch &L, const RedBlock *blocks, int nb
                              const int32_t *slot_idx, const float *part, const float *scale_all,
                              float factor, float *out) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fwd_reduce_kernel, dim3(nblocks), dim3(kThreads), 0, L.stream, blocks,
+  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((16 * L.ncols + kThreads - 1) / kThreads, nblocks),
+                     dim3(kThreads), 0, L.stream, blocks,
                      slot_idx, part, scale_all, factor, L.R, L.c0, L.ncols, out);
   return hipGetLastError();
 }

@@ -71,6 +71,21 @@ struct FwdItem {
   int32_t slot0;    // first partial slot (16 x RP floats each)
 };
 
+// Segment record of the streaming hadronic forward: one group of one item
+// in a workgroup's static work list (items in list order, groups in order).
+struct StreamSeg {
+  const uint4 *a0;    // block 0 of the item: packed group tile at alpha = 0
+  const uint4 *a1;    // block 1, nullptr when the item has one block
+  int32_t nv0, nv1;   // rows of the two blocks (nv1 = 0: absent)
+  int32_t KE, T;      // units per row, k-steps (ceil(KE / 4))
+  int32_t flav;       // row flavour a: the PDF row of the epilogue
+  int32_t last;       // 1 on the item's last group: write its partial sums
+  int64_t bop_off;    // staged B operand of the group, in 16-byte units
+  int32_t slot;       // first partial slot of the item
+  int32_t pad;
+};
+constexpr int kStreamW = 16;  // k-steps in flight per wave in the stream kernel
+
 // Hadronic adjoint item: one group, blocks [block0, block1) of its table.
 struct HadAdjItem {
   int32_t seg;
@@ -112,7 +127,13 @@ struct ConvLaunch {
 constexpr int kZeroPageBytes = 4096;
 
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
-                          const float *gout, const float *scale_all, uint4 *bop, int *counter);
+                          const float *gout, const float *scale_all, uint4 *bop, int *counter,
+                          float *fstage = nullptr, int nflav = 0, int nx = 0);
+// LDS of the stream kernel for (nt, nx, maxT); 0 when it does not fit.
+size_t had_stream_lds_bytes(int nt, int nx, int maxT);
+hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const int32_t *wg_ptr,
+                             int grid, const uint4 *bop, const float *fstage, int nx, int maxT,
+                             float *part);
 hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, const float *pdf, int nx,
                           int lds_units, float *part, int *counter, int grid);

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 using namespace fk;
@@ -232,6 +233,69 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     items.swap(sorted);
   }
 
+  // ---- static work lists of the streaming hadronic forward: items go, in
+  // the order above, to the least loaded of one workgroup per compute unit;
+  // each workgroup walks its items' groups as one list of records.  Every
+  // group must last kStreamW k-steps per wave, so that an LDS buffer is
+  // released before the copy that reuses it is issued.
+  int ncu = 0;
+  FK_TRY_HIP(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  ncu = std::max(ncu, 1);
+  std::vector<StreamSeg> srec;
+  std::vector<int32_t> wgptr;
+  p.grid_stream = 0;
+  if (had && X >= kWaves && !items.empty()) {
+    int minT = 1 << 30;
+    for (const auto &it : items)
+      for (int sg = it.seg0; sg < it.seg1; ++sg) minT = std::min(minT, (segs[sg].KE + 3) / 4);
+    if (minT * (X / kWaves) >= kStreamW) {
+      const int G = std::min<int>(ncu, (int)items.size());
+      const int nal = (X + kWaves - 1) / kWaves;
+      std::vector<std::vector<int>> lists(G);
+      std::vector<std::pair<double, int>> heap;  // (load, workgroup), min-heap
+      for (int g = 0; g < G; ++g) heap.push_back({0.0, g});
+      auto cmp = [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+        return x.first != y.first ? x.first > y.first : x.second > y.second;
+      };
+      std::make_heap(heap.begin(), heap.end(), cmp);
+      for (size_t k = 0; k < items.size(); ++k) {
+        double cost = 16.0;  // combine and write of the item's partial sums
+        for (int sg = items[k].seg0; sg < items[k].seg1; ++sg)
+          cost += (double)((segs[sg].KE + 3) / 4) * nal + 4.0;
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        lists[heap.back().second].push_back((int)k);
+        heap.back().first += cost;
+        std::push_heap(heap.begin(), heap.end(), cmp);
+      }
+      wgptr.push_back(0);
+      for (int g = 0; g < G; ++g) {
+        for (int k : lists[g]) {
+          const FwdItem &it = items[k];
+          const int nv0 = std::min(16, it.ndata - 16 * it.block0);
+          const int nv1 = it.nblk > 1 ? std::min(16, it.ndata - 16 * (it.block0 + 1)) : 0;
+          for (int sg = it.seg0; sg < it.seg1; ++sg) {
+            const SegRef &sr = segs[sg];
+            StreamSeg r;
+            std::memset(&r, 0, sizeof r);
+            r.a0 = sr.base + (size_t)it.block0 * X * 16 * sr.KE;
+            r.a1 = nv1 ? sr.base + (size_t)(it.block0 + 1) * X * 16 * sr.KE : nullptr;
+            r.nv0 = nv0;
+            r.nv1 = nv1;
+            r.KE = sr.KE;
+            r.T = (sr.KE + 3) / 4;
+            r.flav = gd[sr.gdesc].a;
+            r.last = sg == it.seg1 - 1;
+            r.bop_off = gd[sr.gdesc].bop_off;
+            r.slot = it.slot0;
+            srec.push_back(r);
+          }
+        }
+        wgptr.push_back((int32_t)srec.size());
+      }
+      p.grid_stream = G;
+    }
+  }
+
   // ---- adjoint items and the CSR of partial rows per output row (a, x)
   std::vector<std::vector<int64_t>> rows_out((size_t)F * X);
   std::vector<HadAdjItem> hadj;
@@ -312,6 +376,10 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   if ((st = upload(c, p, row_ptr, &p.d_arow_ptr))) return st;
   if ((st = upload(c, p, entries, &p.d_aentry))) return st;
   if ((st = upload(c, p, scale_all, &p.d_scale))) return st;
+  if (p.grid_stream) {
+    if ((st = upload(c, p, srec, &p.d_srec))) return st;
+    if ((st = upload(c, p, wgptr, &p.d_wgptr))) return st;
+  }
   p.nfitems = (int)items.size();
   p.nrblocks = (int)rblocks.size();
   p.nhadj = (int)hadj.size();
@@ -328,9 +396,11 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   if ((st = dev_alloc(c, 64, &d, &p.allocs))) return st;
   p.d_counter = (int *)d;
   FK_TRY_HIP(c, hipMemset(p.d_counter, 0, 64));
-  int ncu = 0;
-  FK_TRY_HIP(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
-  p.grid_fwd = 2 * std::max(ncu, 1);
+  if (p.grid_stream) {
+    if ((st = dev_alloc(c, (size_t)F * X * kRpMax * 4, &d, &p.allocs))) return st;
+    p.d_fstage = (float *)d;
+  }
+  p.grid_fwd = 2 * ncu;
   p.bytes = 0;
   for (auto &a : p.allocs) p.bytes += a.second;
   return FK_OK;
@@ -371,11 +441,22 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
     const int ncols = std::min(kRpMax, nrep - c0);
     ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
+    // FKCONV_NO_STREAM selects the persistent forward kernel everywhere
+    // (both give bitwise the same result; the switch exists for comparing)
+    const bool stream = p.kind == FK_HAD && p.grid_stream > 0 &&
+                        had_stream_lds_bytes(L.nt, p.X, p.maxT_fwd) > 0 &&
+                        !std::getenv("FKCONV_NO_STREAM");
     hipError_t e = timed(tm, FK_K_STAGE, s, [&] {
-      return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, p.d_counter);
+      return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, p.d_counter,
+                            stream ? p.d_fstage : nullptr, p.F, p.X);
     });
     if (e != hipSuccess) return e;
-    if (p.kind == FK_HAD)
+    if (stream)
+      e = timed(tm, FK_K_HAD_FWD, s, [&] {
+        return launch_had_stream(L, p.d_srec, p.d_wgptr, p.grid_stream, p.d_bop, p.d_fstage, p.X,
+                                 p.maxT_fwd, p.d_fpart);
+      });
+    else if (p.kind == FK_HAD)
       e = timed(tm, FK_K_HAD_FWD, s, [&] {
         return launch_had_fwd(L, p.d_fitems, p.nfitems, p.d_seg, p.d_gd, p.d_bop, pdf, p.X,
                               4 * p.maxT_fwd * RP, p.d_fpart, p.d_counter, p.grid_fwd);

@@ -63,6 +63,11 @@ struct Plan {
   void *d_zero = nullptr;  // kZeroPageBytes of zeros read by lanes outside a tile
   int *d_counter = nullptr;  // work counter of the persistent forward kernel
   int grid_fwd = 512;        // persistent workgroups (2 per compute unit)
+  // streaming hadronic forward: per-workgroup segment records
+  StreamSeg *d_srec = nullptr;
+  int32_t *d_wgptr = nullptr;
+  int grid_stream = 0;        // 0: the plan does not use the stream kernel
+  float *d_fstage = nullptr;  // [F][X][RP] FP32 PDF rows of the epilogue
   int maxT_fwd = 1, maxT_adj = 1;
   // bookkeeping
   std::vector<std::pair<void *, size_t>> allocs;

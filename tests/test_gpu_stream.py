@@ -1,0 +1,69 @@
+"""The streaming hadronic forward kernel against the persistent one and the
+oracle.  Both kernels accumulate every item in the same order, so their
+outputs must agree bit for bit; the persistent kernel is selected with the
+FKCONV_NO_STREAM environment variable.  The cases use the hadronic fit
+shape (x-grid of 50, groups of at least two k-steps), where the stream
+kernel applies, over replica counts that select every column-tile count."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_10547_amd import fkconv, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(c, h, x, stream):
+    if stream:
+        os.environ.pop("FKCONV_NO_STREAM", None)
+    else:
+        os.environ["FKCONV_NO_STREAM"] = "1"
+    try:
+        y = fkconv.fk_conv_had(c.ctx, h, x)
+        torch.cuda.synchronize()
+    finally:
+        os.environ.pop("FKCONV_NO_STREAM", None)
+    return y
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f32", "e4m3"])
+@pytest.mark.parametrize("R", [1, 16, 100, 200])
+def test_stream_equals_persistent_and_oracle(fmt, R):
+    w = synth.had_fit_workload(scale=0.12)
+    tabs = [w.table(d) for d in range(len(w.ndata))]
+    pdf = w.pdf(R).astype(np.float32).astype(np.float64)
+    say(f"case fmt={fmt} R={R} ndata={[t.ndata for t in tabs]}")
+    with fkconv.Context(0) as c:
+        hs = [c.load(t, fmt) for t in tabs]
+        g = fkconv.fk_group_create(c.ctx, hs)
+        x = torch.from_numpy(pdf.astype(np.float32)).cuda()
+        ys = run(c, g, x, True)
+        yp = run(c, g, x, False)
+        assert torch.equal(ys, yp), f"stream and persistent kernels differ (fmt={fmt}, R={R})"
+        # every member alone equals its rows of the group
+        off = 0
+        for t, h in zip(tabs, hs):
+            y1 = run(c, h, x, True)
+            assert torch.equal(y1, ys[off:off + t.ndata])
+            off += t.ndata
+        fkconv.fk_unload_table(c.ctx, g)
+        for h in hs:
+            fkconv.fk_unload_table(c.ctx, h)
+    got = ys.double().cpu().numpy()
+    q = np.concatenate([oracle.had_quantized(t.mask, t.fk, pdf, fmt)
+                        for t in tabs])
+    absterms = np.concatenate([oracle.had(t.mask, np.abs(t.fk), np.abs(pdf)) for t in tabs])
+    e = float(np.max(np.abs(got - q) / absterms))
+    say(f"  bitwise equal to the persistent kernel; stored-operand error {e:.2e} of sum|terms|")
+    # FP32 summation bound, as for the other stored-operand gates; the FP8
+    # MFMA gets the looser gate of the FP8 forward tests
+    assert e <= (1e-4 if fmt == "e4m3" else 1e-5)
