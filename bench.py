@@ -94,8 +94,11 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip DIS/adjoint/chi2 rows")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving rows")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="serving: 10k requests at each of 6 rates (default: 2k requests, 2 rates)")
+    ap.add_argument("--serve-quick", action="store_true",
+                    help="serving: 2k requests at 2 rates (default: 10k requests at each of 6 rates)")
+    ap.add_argument("--no-rsweep", action="store_true", help="skip the replica-count sweep")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured HBM-copy and BF16-GEMM ceilings")
     ap.add_argument("--no-dis-hbm", action="store_true",
                     help="skip the large DIS set used for the HBM-bandwidth rows")
     ap.add_argument("--dis-hbm-gib", type=float, default=2.0,
@@ -267,6 +270,21 @@ def main() -> int:
             "sample": f"{nsamp} of {Ntot} datapoints (evenly spaced in every dataset) x {R} replicas, FP64, "
                       f"{passes} pass(es) in {el:.1f}s",
         }
+        # the same oracle on one thread, on the first datasets' sample rows
+        nth = oracle.num_threads()
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        n1 = 0
+        for t, sel in zip(tabs, sels):
+            sel1 = sel[: max(1, len(sel) // 8)]
+            oracle.had(t.mask, t.fk[sel1], pdf64)
+            n1 += len(sel1)
+            if time.perf_counter() - t0 > 0.5 * args.cpu_seconds:
+                break
+        el1 = time.perf_counter() - t0
+        oracle.set_num_threads(nth)
+        result["cpu_baseline"]["value_1thread"] = n1 * R / el1
+        result["cpu_baseline"]["sample_1thread"] = f"{n1} datapoints x {R} replicas, FP64, 1 thread, {el1:.1f}s"
         result["error"].update({
             "bf16_vs_fp64_sample_normwise": normwise(np.concatenate(gotb), ref),
             "fp32_vs_fp64_sample_normwise": normwise(np.concatenate(gotf), ref),
@@ -277,9 +295,19 @@ def main() -> int:
         except (OSError, IndexError):
             pass
 
+    if not args.no_peaks:
+        log("measured ceilings: HBM copy, BF16 GEMM")
+        pk = measured_peaks(torch)
+        result["measured_peaks"] = pk
+        result["roofline"]["frac_of_measured"] = achieved / pk["hbm_copy_gbs"]
+    if not args.no_rsweep:
+        log("replica sweep")
+        result.setdefault("rows", {})["had_bf16_rsweep"] = rsweep(c, w, gb, elems_fwd, Ntot, args, torch,
+                                                                  fkconv)
     if not args.no_extras:
         log("extra rows: DIS, adjoints, chi2, fit step")
-        result["rows"] = extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth)
+        result.setdefault("rows", {}).update(extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv,
+                                                    synth))
     if not args.no_serve:
         log("serving")
         result.setdefault("rows", {})["serving"] = serving(c, w, tabs, args, torch, fkconv, synth)
@@ -352,10 +380,10 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
             (tab, Rs, prec, outs, pseed)
 
     res = {}
-    nreq = 10000 if args.serve_full else 2000
+    nreq = 2000 if args.serve_quick else 10000
     cap, sample = run(nreq, None)
     res["closed_loop"] = cap
-    fracs = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2) if args.serve_full else (0.5, 0.9)
+    fracs = (0.5, 0.9) if args.serve_quick else (0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
     for f in fracs:
         r, sample = run(nreq, f * cap["req_per_s"])
         res[f"rate_{f:g}x"] = r
@@ -371,6 +399,60 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
     for h in hb + hf:
         fkconv.fk_unload_table(c.ctx, h)
     return res
+
+
+def measured_peaks(torch):
+    """Ceilings measured on this GPU with library kernels: a 4 GiB device copy
+    (HBM read + write) and an 8192^3 BF16 GEMM (hipBLASLt)."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * 4 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    m = 8192
+    x = torch.randn((m, m), dtype=torch.bfloat16, device="cuda")
+    y = torch.randn((m, m), dtype=torch.bfloat16, device="cuda")
+    for _ in range(3):
+        z = x @ y
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        z = x @ y
+    e1.record()
+    torch.cuda.synchronize()
+    tflops = 20 * 2.0 * m ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del x, y, z
+    torch.cuda.empty_cache()
+    return {"hbm_copy_gbs": copy_gbs, "bf16_gemm_tflops": tflops,
+            "note": "4 GiB float32 device copy counted as read + write; torch.matmul BF16 8192^3"}
+
+
+def rsweep(c, w, gb, elems_fwd, Ntot, args, torch, fkconv):
+    """The hadronic BF16 step at more replicas.  Columns are processed in
+    passes of 128, each streaming the table once."""
+    out = {}
+    for R in (256, 512, 1024):
+        x = torch.from_numpy(w.pdf(R).astype(np.float32)).cuda()
+        y = torch.empty((Ntot, R), dtype=torch.float32, device="cuda")
+        fn = lambda: fkconv.fk_conv_had(c.ctx, gb, x, out=y)
+        ms, per = time_steps(fn, max(5, args.steps // 2), 3, torch)
+        kt = kernel_times(c, fn, max(5, args.steps // 2), torch, fkconv)
+        kms = kt["had_fwd"][0] / max(5, args.steps // 2)  # all passes of one step
+        tfl = 2.0 * elems_fwd * R / (kms * 1e-3) / 1e12
+        out[f"R{R}"] = {"ms_per_step": ms, "value": Ntot * R / (ms * 1e-3),
+                        "had_fwd_ms_per_step": kms, "passes": (R + 127) // 128,
+                        "mfma_tflops": tfl, "mfma_frac": tfl / PEAK_BF16_TFLOPS}
+    return out
 
 
 def dis_hbm(c, args, torch, fkconv, synth):

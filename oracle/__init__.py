@@ -82,6 +82,8 @@ def _load():
         lib.oracle_cholesky.restype = I
         lib.oracle_chi2.argtypes = [I, P, P, I, P, P, P, P]
         lib.oracle_num_threads.restype = I
+        lib.oracle_set_num_threads.argtypes = [I]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -100,6 +102,12 @@ def _p(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (one thread per output, so the
+    results do not depend on it)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -241,3 +241,14 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads for the parallel loops that follow (timing only: every output is
+   computed by one thread, so results do not depend on the count). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
