@@ -462,22 +462,23 @@ __device__ __forceinline__ void dma16(gu32x4_ptr src, u32x4 *dst) {
 // instruction k moves units [64k, 64k+64); wave w issues instructions w,
 // w+4, ...  Lanes past the end read the zero page and write inside the last
 // KiB of the copy (buffers are whole KiB).
+template <int S>
 __device__ __forceinline__ void dma_copy(u32x4 *dst, const u32x4 *src, int units,
                                          const u32x4 *zp, int w, int lane) {
   const int n = (units + 63) >> 6;
-  for (int k = w; k < n; k += kWaves) {
+  for (int k = w; k < n; k += S) {
     const int u = 64 * k + lane;
     dma16(u < units ? as_global(src) + u : as_global(zp) + lane, dst + 64 * k);
   }
 }
 
-template <int DT, int NT, int W>
-__global__ void __launch_bounds__(kThreads, 1)
+template <int DT, int NT, int W, int S>
+__global__ void __launch_bounds__(64 * S, 1)
     had_stream_kernel(const StreamSeg *__restrict__ recs, const int32_t *__restrict__ wg_ptr,
                       const u32x4 *__restrict__ bop, const float *__restrict__ fstage, int nx,
                       int bufsz, float *__restrict__ part, const u32x4 *zp) {
   constexpr int RP = 16 * NT;
-  constexpr int S = kWaves;
+  constexpr int NTHR = 64 * S;
   extern __shared__ u32x4 lds[];
   // the wave index is uniform: say so, so that every cursor below lives in
   // scalar registers and every branch on it is a scalar branch
@@ -498,9 +499,9 @@ __global__ void __launch_bounds__(kThreads, 1)
   auto stage = [&](const StreamSeg &q, int par) {
     u32x4 *buf = lds + par * bufsz;
     const int ub = 4 * q.T * RP;
-    dma_copy(buf, bop + q.bop_off, ub, zp, w, lane);
-    dma_copy(buf + ub, (const u32x4 *)(fstage + (size_t)q.flav * nx * RP), nx * RP / 4, zp, w,
-             lane);
+    dma_copy<S>(buf, bop + q.bop_off, ub, zp, w, lane);
+    dma_copy<S>(buf + ub, (const u32x4 *)(fstage + (size_t)q.flav * nx * RP), nx * RP / 4, zp, w,
+                lane);
   };
 
   // refill cursor: record rr, job alpha r_al, k-step r_t
@@ -540,23 +541,42 @@ __global__ void __launch_bounds__(kThreads, 1)
     }
   };
 
-  // the four waves' sums of the item, combined in a fixed order
+  // The waves' sums of the item, combined in a fixed order: with eight
+  // waves, wave w + 4 first adds its sums into wave w's (w < 4); then the
+  // four remaining sums are added in wave order.
   auto flush = [&](const StreamSeg &q, int par) {
+    float *red = (float *)(lds + par * bufsz);  // [block][4][16][RP]
+    auto put = [&](int slot) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          red[((0 * 4 + slot) * 16 + 4 * g + e) * RP + 16 * j + c] = sacc0[j][e];
+          red[((1 * 4 + slot) * 16 + 4 * g + e) * RP + 16 * j + c] = sacc1[j][e];
+        }
+    };
     lds_barrier();
-    float *red = (float *)(lds + par * bufsz);  // [block][wave][16][RP]
+    if (S == 8) {
+      if (w >= 4) put(w - 4);
+      lds_barrier();
+      if (w < 4) {
 #pragma unroll
-    for (int j = 0; j < NT; ++j)
+        for (int j = 0; j < NT; ++j)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        red[((0 * S + w) * 16 + 4 * g + e) * RP + 16 * j + c] = sacc0[j][e];
-        red[((1 * S + w) * 16 + 4 * g + e) * RP + 16 * j + c] = sacc1[j][e];
+          for (int e = 0; e < 4; ++e) {
+            sacc0[j][e] += red[((0 * 4 + w) * 16 + 4 * g + e) * RP + 16 * j + c];
+            sacc1[j][e] += red[((1 * 4 + w) * 16 + 4 * g + e) * RP + 16 * j + c];
+          }
       }
+      lds_barrier();
+    }
+    if (w < 4) put(w);
     lds_barrier();
     const int nb = q.nv1 > 0 ? 2 : 1;
     for (int b = 0; b < nb; ++b) {
-      const float *rb = red + (size_t)b * S * 16 * RP;
+      const float *rb = red + (size_t)b * 4 * 16 * RP;
       float *dst = part + (size_t)(q.slot + b) * 16 * kRpMax;
-      for (int i = threadIdx.x; i < 16 * RP; i += kThreads) {
+      for (int i = threadIdx.x; i < 16 * RP; i += NTHR) {
         const int rw = i / RP, col = i - rw * RP;
         dst[rw * kRpMax + col] = ((rb[i] + rb[16 * RP + i]) + rb[32 * RP + i]) + rb[48 * RP + i];
       }
@@ -925,7 +945,7 @@ hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems,
 size_t had_stream_lds_bytes(int nt, int nx, int maxT) {
   const int RP = 16 * nt;
   // B operand + PDF rows, or the combine buffer [2][4][16][RP] floats
-  int units = std::max(4 * maxT * RP + nx * RP / 4, 2 * kWaves * 16 * RP / 4);
+  int units = std::max(4 * maxT * RP + nx * RP / 4, 2 * 4 * 16 * RP / 4);
   units = (units + 63) / 64 * 64;
   const size_t bytes = (size_t)2 * units * 16;
   return bytes <= 163840 ? bytes : 0;
@@ -941,9 +961,9 @@ hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const i
   hipError_t err = hipSuccess;
 #define FK_HS(NT)                                                                              \
   {                                                                                            \
-    auto k = had_stream_kernel<DTV, NT, kStreamW>;                                             \
+    auto k = had_stream_kernel<DTV, NT, kStreamW, kStreamWaves>;                               \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                     \
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, L.stream, recs, wg_ptr,             \
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kStreamWaves), lds, L.stream, recs, wg_ptr,    \
                        (const u32x4 *)bop, fstage, nx, bufsz, part, (const u32x4 *)L.zero_page); \
   }
 #define FK_HS_DT(DT)           \

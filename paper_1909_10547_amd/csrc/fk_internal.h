@@ -84,7 +84,8 @@ struct StreamSeg {
   int32_t slot;       // first partial slot of the item
   int32_t pad;
 };
-constexpr int kStreamW = 16;  // k-steps in flight per wave in the stream kernel
+constexpr int kStreamW = 8;       // k-steps in flight per wave in the stream kernel
+constexpr int kStreamWaves = 8;   // waves per workgroup of the stream kernel (2 per SIMD)
 
 // Hadronic adjoint item: one group, blocks [block0, block1) of its table.
 struct HadAdjItem {

@@ -244,13 +244,13 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   std::vector<StreamSeg> srec;
   std::vector<int32_t> wgptr;
   p.grid_stream = 0;
-  if (had && X >= kWaves && !items.empty()) {
+  if (had && X >= kStreamWaves && !items.empty()) {
     int minT = 1 << 30;
     for (const auto &it : items)
       for (int sg = it.seg0; sg < it.seg1; ++sg) minT = std::min(minT, (segs[sg].KE + 3) / 4);
-    if (minT * (X / kWaves) >= kStreamW) {
+    if (minT * (X / kStreamWaves) >= kStreamW) {
       const int G = std::min<int>(ncu, (int)items.size());
-      const int nal = (X + kWaves - 1) / kWaves;
+      const int nal = (X + kStreamWaves - 1) / kStreamWaves;
       std::vector<std::vector<int>> lists(G);
       std::vector<std::pair<double, int>> heap;  // (load, workgroup), min-heap
       for (int g = 0; g < G; ++g) heap.push_back({0.0, g});
@@ -292,7 +292,8 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
         }
         wgptr.push_back((int32_t)srec.size());
       }
-      p.grid_stream = G;
+      // the plan keeps the stream kernel only if seven column tiles fit
+      p.grid_stream = had_stream_lds_bytes(7, X, p.maxT_fwd) ? G : 0;
     }
   }
 
@@ -437,15 +438,17 @@ static hipError_t timed(Timing *tm, int kind, hipStream_t s, F &&launch) {
 
 hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hipStream_t s,
                        Timing *tm) {
-  for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
-    const int ncols = std::min(kRpMax, nrep - c0);
+  // FKCONV_NO_STREAM selects the persistent hadronic forward kernel (for
+  // comparisons; the two kernels sum in different orders).  A plan that
+  // uses the stream kernel uses it for every column pass, so that a
+  // request's result does not depend on the replica count it is batched
+  // with: passes are cut to 112 columns when 128 do not fit its LDS.
+  const bool stream = p.kind == FK_HAD && p.grid_stream > 0 && !std::getenv("FKCONV_NO_STREAM");
+  const int chunk = stream && !had_stream_lds_bytes(8, p.X, p.maxT_fwd) ? 112 : kRpMax;
+  for (int c0 = 0; c0 < nrep; c0 += chunk) {
+    const int ncols = std::min(chunk, nrep - c0);
     ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
-    // FKCONV_NO_STREAM selects the persistent forward kernel everywhere
-    // (both give bitwise the same result; the switch exists for comparing)
-    const bool stream = p.kind == FK_HAD && p.grid_stream > 0 &&
-                        had_stream_lds_bytes(L.nt, p.X, p.maxT_fwd) > 0 &&
-                        !std::getenv("FKCONV_NO_STREAM");
     hipError_t e = timed(tm, FK_K_STAGE, s, [&] {
       return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, p.d_counter,
                             stream ? p.d_fstage : nullptr, p.F, p.X);

@@ -1,9 +1,12 @@
 """The streaming hadronic forward kernel against the persistent one and the
-oracle.  Both kernels accumulate every item in the same order, so their
-outputs must agree bit for bit; the persistent kernel is selected with the
-FKCONV_NO_STREAM environment variable.  The cases use the hadronic fit
-shape (x-grid of 50, groups of at least two k-steps), where the stream
-kernel applies, over replica counts that select every column-tile count."""
+oracle.  The two kernels split the x index over different numbers of waves,
+so they sum in different orders: each must be within the FP32 summation
+bound of the stored-operand oracle, and the stream kernel must be
+deterministic and give every member table bitwise its rows of a group.  The
+persistent kernel is selected with the FKCONV_NO_STREAM environment
+variable.  The cases use the hadronic fit shape (x-grid of 50, groups of at
+least two k-steps), where the stream kernel applies, over replica counts
+that select every column-tile count."""
 import os
 import sys
 
@@ -48,7 +51,7 @@ def test_stream_equals_persistent_and_oracle(fmt, R):
         x = torch.from_numpy(pdf.astype(np.float32)).cuda()
         ys = run(c, g, x, True)
         yp = run(c, g, x, False)
-        assert torch.equal(ys, yp), f"stream and persistent kernels differ (fmt={fmt}, R={R})"
+        assert torch.equal(run(c, g, x, True), ys), "stream kernel is not deterministic"
         # every member alone equals its rows of the group
         off = 0
         for t, h in zip(tabs, hs):
@@ -58,12 +61,13 @@ def test_stream_equals_persistent_and_oracle(fmt, R):
         fkconv.fk_unload_table(c.ctx, g)
         for h in hs:
             fkconv.fk_unload_table(c.ctx, h)
-    got = ys.double().cpu().numpy()
     q = np.concatenate([oracle.had_quantized(t.mask, t.fk, pdf, fmt)
                         for t in tabs])
     absterms = np.concatenate([oracle.had(t.mask, np.abs(t.fk), np.abs(pdf)) for t in tabs])
-    e = float(np.max(np.abs(got - q) / absterms))
-    say(f"  bitwise equal to the persistent kernel; stored-operand error {e:.2e} of sum|terms|")
     # FP32 summation bound, as for the other stored-operand gates; the FP8
     # MFMA gets the looser gate of the FP8 forward tests
-    assert e <= (1e-4 if fmt == "e4m3" else 1e-5)
+    tol = 1e-4 if fmt == "e4m3" else 1e-5
+    for name, y in (("stream", ys), ("persistent", yp)):
+        e = float(np.max(np.abs(y.double().cpu().numpy() - q) / absterms))
+        say(f"  {name}: stored-operand error {e:.2e} of sum|terms|")
+        assert e <= tol, name
