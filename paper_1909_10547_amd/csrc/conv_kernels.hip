@@ -711,6 +711,132 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ---------------------------------------------------------------------------
+// Streaming DIS forward.  A workgroup owns a range of 16-datapoint blocks of
+// one table; it copies the B operands of all the table's groups into LDS
+// once (group after group, so k-step q of a block reads B at 4q), then each
+// wave streams whole block rows -- blocks w, w+S, ... of the range, every
+// group of a block in turn -- through a ring of W k-steps in registers and
+// writes s_i times the dot product straight to the output.  No barrier and
+// no partial sums: the contraction of a row is one accumulation chain.
+// ---------------------------------------------------------------------------
+template <int DT, int NT, int W, int S>
+__global__ void __launch_bounds__(64 * S)
+    dis_stream_kernel(const DisStreamWG *__restrict__ wgs, const DisGroupRef *__restrict__ groups,
+                      const u32x4 *__restrict__ bop, const float *__restrict__ scale_all, int R,
+                      int c0, int ncols, float *__restrict__ out, const u32x4 *zp) {
+  constexpr int RP = 16 * NT;
+  extern __shared__ u32x4 lds[];
+  const DisStreamWG wg = wgs[blockIdx.x];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const gu32x4_ptr zpg = as_global(zp);
+  // B of every group, then the scales of the range's datapoints; each
+  // thread issues up to eight loads before it stores any
+  constexpr int NTHR = 64 * S;
+  float *sl = (float *)(lds + 4 * wg.ttot * RP);
+  {
+    int off = 0;
+    for (int gi = wg.g0; gi < wg.g1; ++gi) {
+      const int n = 4 * groups[gi].T * RP;
+      const u32x4 *src = bop + groups[gi].bop_off;
+      for (int i0 = threadIdx.x; i0 < n; i0 += 8 * NTHR) {
+        u32x4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (i0 + k * NTHR < n) v[k] = src[i0 + k * NTHR];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (i0 + k * NTHR < n) lds[off + i0 + k * NTHR] = v[k];
+      }
+      off += n;
+    }
+    const int nrow = min(16 * wg.nblk, wg.ndata - 16 * wg.block0);
+    const float *ssrc = scale_all + wg.orow0 + 16 * wg.block0;
+    for (int i0 = threadIdx.x; i0 < nrow; i0 += 8 * NTHR) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (i0 + k * NTHR < nrow) v[k] = ssrc[i0 + k * NTHR];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (i0 + k * NTHR < nrow) sl[i0 + k * NTHR] = v[k];
+    }
+  }
+  __syncthreads();
+  if (w >= wg.nblk) return;  // no block for this wave (after the barrier)
+
+  u32x4 a[W];
+  f32x4 acc[NT];
+  zero(acc);
+
+  // refill cursor: block rb (relative), group rg, k-step rt of the group
+  int rb = w, rg = wg.g0, rt = 0;
+  bool r_done = false;
+  DisGroupRef G = groups[rg];
+  int rnv = min(16, wg.ndata - 16 * (wg.block0 + rb));
+  gu32x4_ptr pa = as_global(G.base) + (size_t)(wg.block0 + rb) * 16 * G.KE;
+  auto refill = [&](u32x4 &x) {
+    const int u = 4 * rt + g;
+    const bool ok = !r_done && c < rnv && u < G.KE;
+    x = __builtin_nontemporal_load(ok ? pa + (u * rnv + c) : zpg + lane);
+    if (!r_done && ++rt == G.T) {
+      rt = 0;
+      if (++rg == wg.g1) {
+        rg = wg.g0;
+        rb += S;
+        if (rb >= wg.nblk) r_done = true;
+        else rnv = min(16, wg.ndata - 16 * (wg.block0 + rb));
+      }
+      G = groups[rg];
+      pa = as_global(G.base) + (size_t)(wg.block0 + rb) * 16 * G.KE;
+    }
+  };
+  // consume cursor: block cb, k-step q over all groups of the block
+  int cb = w, q = 0;
+  bool done = false;
+  auto consume = [&](const u32x4 &x) {
+    if (done) return;
+    const u32x4 *bp = lds + (4 * q + g) * RP + c;
+    u32x4 b[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) b[j] = bp[16 * j];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) Mma<DT>::run(x, b[j], acc[j]);
+    if (++q == wg.ttot) {
+      q = 0;
+      const int row0 = 16 * cb;  // first row of the block within the range
+      const int nv = min(16, wg.ndata - 16 * (wg.block0 + cb));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 4 * g + e;
+        if (r < nv) {
+          const float sc = sl[row0 + r];
+          float *o = out + (size_t)(wg.orow0 + 16 * (wg.block0 + cb) + r) * R + c0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            if (16 * j + c < ncols) o[16 * j + c] = sc * acc[j][e];
+        }
+      }
+      zero(acc);
+      cb += S;
+      if (cb >= wg.nblk) done = true;
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < W; ++i) refill(a[i]);
+  // single exit at the end of the unrolled body (see had_stream_kernel)
+  do {
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      consume(a[i]);
+      refill(a[i]);
+    }
+  } while (!done);
+  wait_vmcnt<0>();
+}
+
+// ---------------------------------------------------------------------------
 // Hadronic adjoint: H = Shat f per (block, alpha) tile, weighted by
 // W[i,r] = gbar[i,r] s_i and summed over the tile's datapoints.
 // ---------------------------------------------------------------------------
@@ -974,6 +1100,37 @@ hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const i
   FK_DISPATCH_DT(FK_HS_DT);
 #undef FK_HS
 #undef FK_HS_DT
+  return hipGetLastError();
+}
+
+size_t dis_stream_lds_bytes(int nt, int ttot_max) {
+  const size_t bytes = (size_t)4 * ttot_max * 16 * nt * 16 + (size_t)16 * kDisStreamMaxBlk * 4;
+  return bytes <= 163840 ? bytes : 0;
+}
+
+hipError_t launch_dis_stream(const ConvLaunch &L, const DisStreamWG *wgs, int nwg,
+                             const DisGroupRef *groups, const uint4 *bop, const float *scale_all,
+                             int ttot_max, float *out) {
+  if (nwg <= 0) return hipSuccess;
+  const size_t lds = dis_stream_lds_bytes(L.nt, ttot_max);
+  if (!lds) return hipErrorInvalidValue;
+  hipError_t err = hipSuccess;
+#define FK_DS(NT)                                                                              \
+  {                                                                                            \
+    auto k = dis_stream_kernel<DTV, NT, kDisStreamW, kDisStreamWaves>;                         \
+    if ((err = set_lds(k, lds)) != hipSuccess) return err;                                     \
+    hipLaunchKernelGGL(k, dim3(nwg), dim3(64 * kDisStreamWaves), lds, L.stream, wgs, groups,   \
+                       (const u32x4 *)bop, scale_all, L.R, L.c0, L.ncols, out,                 \
+                       (const u32x4 *)L.zero_page);                                            \
+  }
+#define FK_DS_DT(DT)           \
+  {                            \
+    constexpr int DTV = DT;    \
+    FK_DISPATCH_NT(FK_DS);     \
+  }
+  FK_DISPATCH_DT(FK_DS_DT);
+#undef FK_DS
+#undef FK_DS_DT
   return hipGetLastError();
 }
 

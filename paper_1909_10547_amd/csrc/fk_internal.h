@@ -87,6 +87,27 @@ struct StreamSeg {
 constexpr int kStreamW = 8;       // k-steps in flight per wave in the stream kernel
 constexpr int kStreamWaves = 8;   // waves per workgroup of the stream kernel (2 per SIMD)
 
+// DIS stream kernel: one group of a table (forward groups in k order).
+struct DisGroupRef {
+  const uint4 *base;  // packed group, block 0
+  int32_t KE, T;      // units per row, k-steps
+  int64_t bop_off;    // staged B operand (16-byte units)
+};
+
+// DIS stream kernel: one workgroup's range of 16-datapoint blocks of one
+// table; the table's groups are [g0, g1) of the plan's DisGroupRef list.
+struct DisStreamWG {
+  int32_t g0, g1;
+  int32_t block0, nblk;  // blocks of the table
+  int32_t ndata;         // datapoints of the table
+  int32_t orow0;         // output row of the table's datapoint 0
+  int32_t ttot;          // k-steps per block over all groups
+  int32_t pad;
+};
+constexpr int kDisStreamW = 16;      // k-steps in flight per wave
+constexpr int kDisStreamWaves = 8;   // waves per workgroup
+constexpr int kDisStreamMaxBlk = 512;  // blocks per workgroup (scales kept in LDS)
+
 // Hadronic adjoint item: one group, blocks [block0, block1) of its table.
 struct HadAdjItem {
   int32_t seg;
@@ -138,6 +159,12 @@ hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const i
 hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, const float *pdf, int nx,
                           int lds_units, float *part, int *counter, int grid);
+// LDS of the DIS stream kernel for (nt, max k-steps per block); 0 when it
+// does not fit.
+size_t dis_stream_lds_bytes(int nt, int ttot_max);
+hipError_t launch_dis_stream(const ConvLaunch &L, const DisStreamWG *wgs, int nwg,
+                             const DisGroupRef *groups, const uint4 *bop, const float *scale_all,
+                             int ttot_max, float *out);
 hipError_t launch_dis_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, int lds_units, float *part);
 hipError_t launch_fwd_reduce(const ConvLaunch &L, const RedBlock *blocks, int nblocks,

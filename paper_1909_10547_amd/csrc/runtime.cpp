@@ -297,6 +297,54 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     }
   }
 
+  // ---- streaming DIS forward: each table's blocks in ranges of about
+  // 1/(2 ncu) of all blocks, one workgroup per range
+  std::vector<DisGroupRef> dgroups;
+  std::vector<DisStreamWG> dwgs;
+  p.dis_chunk = 0;
+  if (!had) {
+    int ttot_max = 0;
+    long total_blk = 0;
+    for (auto *t : ts) total_blk += (t->N + 15) / 16;
+    const int target =
+        (int)std::max<long>(1, std::min<long>(kDisStreamMaxBlk, (total_blk + 2 * ncu - 1) / (2 * ncu)));
+    for (size_t t = 0; t < ts.size(); ++t) {
+      const int g0 = (int)dgroups.size();
+      int ttot = 0;
+      for (int sg : segidx[t]) {
+        DisGroupRef r;
+        r.base = segs[sg].base;
+        r.KE = segs[sg].KE;
+        r.T = (segs[sg].KE + 3) / 4;
+        r.bop_off = gd[segs[sg].gdesc].bop_off;
+        dgroups.push_back(r);
+        ttot += r.T;
+      }
+      ttot_max = std::max(ttot_max, ttot);
+      const int nblk = (ts[t]->N + 15) / 16;
+      const int nr = (nblk + target - 1) / target;
+      for (int k = 0; k < nr; ++k) {
+        DisStreamWG wgd;
+        std::memset(&wgd, 0, sizeof wgd);
+        wgd.g0 = g0;
+        wgd.g1 = (int)dgroups.size();
+        wgd.block0 = (int)((long)nblk * k / nr);
+        wgd.nblk = (int)((long)nblk * (k + 1) / nr) - wgd.block0;
+        wgd.ndata = ts[t]->N;
+        wgd.orow0 = p.row0[t];
+        wgd.ttot = ttot;
+        if (wgd.nblk > 0) dwgs.push_back(wgd);
+      }
+    }
+    p.dis_ttot_max = ttot_max;
+    // one column width for every pass of the plan (see run_forward)
+    for (int nt : {8, 7, 4})
+      if (dis_stream_lds_bytes(nt, ttot_max)) {
+        p.dis_chunk = 16 * nt;
+        break;
+      }
+  }
+
   // ---- adjoint items and the CSR of partial rows per output row (a, x)
   std::vector<std::vector<int64_t>> rows_out((size_t)F * X);
   std::vector<HadAdjItem> hadj;
@@ -381,6 +429,11 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     if ((st = upload(c, p, srec, &p.d_srec))) return st;
     if ((st = upload(c, p, wgptr, &p.d_wgptr))) return st;
   }
+  if (p.dis_chunk) {
+    if ((st = upload(c, p, dgroups, &p.d_dgroups))) return st;
+    if ((st = upload(c, p, dwgs, &p.d_dwgs))) return st;
+    p.n_dwgs = (int)dwgs.size();
+  }
   p.nfitems = (int)items.size();
   p.nrblocks = (int)rblocks.size();
   p.nhadj = (int)hadj.size();
@@ -443,8 +496,11 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
   // uses the stream kernel uses it for every column pass, so that a
   // request's result does not depend on the replica count it is batched
   // with: passes are cut to 112 columns when 128 do not fit its LDS.
-  const bool stream = p.kind == FK_HAD && p.grid_stream > 0 && !std::getenv("FKCONV_NO_STREAM");
-  const int chunk = stream && !had_stream_lds_bytes(8, p.X, p.maxT_fwd) ? 112 : kRpMax;
+  const bool no_stream = std::getenv("FKCONV_NO_STREAM") != nullptr;
+  const bool stream = p.kind == FK_HAD && p.grid_stream > 0 && !no_stream;
+  const bool dstream = p.kind == FK_DIS && p.dis_chunk > 0 && !no_stream;
+  const int chunk = dstream ? p.dis_chunk
+                            : (stream && !had_stream_lds_bytes(8, p.X, p.maxT_fwd) ? 112 : kRpMax);
   for (int c0 = 0; c0 < nrep; c0 += chunk) {
     const int ncols = std::min(chunk, nrep - c0);
     ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
@@ -454,6 +510,15 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
                             stream ? p.d_fstage : nullptr, p.F, p.X);
     });
     if (e != hipSuccess) return e;
+    if (dstream) {
+      // the DIS stream kernel writes the output rows itself
+      e = timed(tm, FK_K_DIS_FWD, s, [&] {
+        return launch_dis_stream(L, p.d_dwgs, p.n_dwgs, p.d_dgroups, p.d_bop, p.d_scale,
+                                 p.dis_ttot_max, out);
+      });
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (stream)
       e = timed(tm, FK_K_HAD_FWD, s, [&] {
         return launch_had_stream(L, p.d_srec, p.d_wgptr, p.grid_stream, p.d_bop, p.d_fstage, p.X,

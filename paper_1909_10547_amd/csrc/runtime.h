@@ -68,6 +68,12 @@ struct Plan {
   int32_t *d_wgptr = nullptr;
   int grid_stream = 0;        // 0: the plan does not use the stream kernel
   float *d_fstage = nullptr;  // [F][X][RP] FP32 PDF rows of the epilogue
+  // streaming DIS forward
+  DisGroupRef *d_dgroups = nullptr;
+  DisStreamWG *d_dwgs = nullptr;
+  int n_dwgs = 0;
+  int dis_ttot_max = 0;
+  int dis_chunk = 0;  // columns per pass of the DIS stream kernel; 0: not used
   int maxT_fwd = 1, maxT_adj = 1;
   // bookkeeping
   std::vector<std::pair<void *, size_t>> allocs;

@@ -71,3 +71,48 @@ def test_stream_equals_persistent_and_oracle(fmt, R):
         e = float(np.max(np.abs(y.double().cpu().numpy() - q) / absterms))
         say(f"  {name}: stored-operand error {e:.2e} of sum|terms|")
         assert e <= tol, name
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f32", "e4m3"])
+@pytest.mark.parametrize("R", [1, 16, 100, 200])
+def test_dis_stream_against_partial_sum_kernel_and_oracle(fmt, R):
+    """DIS: the stream kernel (one accumulation chain per row, written
+    directly) against the partial-sum kernel and the stored-operand oracle."""
+    w = synth.dis_fit_workload(scale=0.15)
+    tabs = [w.table(d) for d in range(len(w.ndata))]
+    pdf = w.pdf(R).astype(np.float32).astype(np.float64)
+    say(f"case DIS fmt={fmt} R={R} ndata={[t.ndata for t in tabs]}")
+    with fkconv.Context(0) as c:
+        hs = [c.load(t, fmt) for t in tabs]
+        g = fkconv.fk_group_create(c.ctx, hs)
+        x = torch.from_numpy(pdf.astype(np.float32)).cuda()
+
+        def dis(h, stream):
+            if stream:
+                os.environ.pop("FKCONV_NO_STREAM", None)
+            else:
+                os.environ["FKCONV_NO_STREAM"] = "1"
+            try:
+                y = fkconv.fk_conv_dis(c.ctx, h, x)
+                torch.cuda.synchronize()
+            finally:
+                os.environ.pop("FKCONV_NO_STREAM", None)
+            return y
+
+        ys = dis(g, True)
+        yp = dis(g, False)
+        assert torch.equal(dis(g, True), ys), "DIS stream kernel is not deterministic"
+        off = 0
+        for t, h in zip(tabs, hs):
+            assert torch.equal(dis(h, True), ys[off:off + t.ndata])
+            off += t.ndata
+        fkconv.fk_unload_table(c.ctx, g)
+        for h in hs:
+            fkconv.fk_unload_table(c.ctx, h)
+    q = np.concatenate([oracle.dis_quantized(t.mask, t.fk, pdf, fmt) for t in tabs])
+    absterms = np.concatenate([oracle.dis(t.mask, np.abs(t.fk), np.abs(pdf)) for t in tabs])
+    tol = 1e-4 if fmt == "e4m3" else 1e-5
+    for name, y in (("stream", ys), ("partial-sum", yp)):
+        e = float(np.max(np.abs(y.double().cpu().numpy() - q) / np.where(absterms > 0, absterms, 1.0)))
+        say(f"  {name}: stored-operand error {e:.2e} of sum|terms|")
+        assert e <= tol, name
