@@ -586,25 +586,33 @@ __global__ void __launch_bounds__(64 * S, 1)
     zero(sacc1);
   };
 
-  // consume cursor: record cr, job alpha c_al, k-step c_t, buffer cpar
+  // consume cursor: record cr, job alpha c_al, k-step c_t, buffer cpar.
+  // The B fragments of a k-step are read right after the MFMAs of the one
+  // before (same registers), so their LDS latency overlaps the epilogue, the
+  // cursor work and the refill.
   int cr = r_begin, c_al = w, c_t = 0, cpar = 0;
   StreamSeg Cq = Rq;
   bool done = false;
-  auto consume = [&](const u32x4 &x0, const u32x4 &x1) {
-    if (done) return;
+  u32x4 b[NT];
+  auto read_b = [&]() {
     const u32x4 *bp = lds + cpar * bufsz + (4 * c_t + g) * RP + c;
-    // all B reads of the k-step first, so their latencies overlap
-    u32x4 b[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) b[j] = bp[16 * j];
-    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto consume = [&](const u32x4 &x0, const u32x4 &x1) {
+    if (done) return;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       Mma<DT>::run(x0, b[j], acc0[j]);
       Mma<DT>::run(x1, b[j], acc1[j]);
     }
-    if (++c_t == Cq.T) {
-      c_t = 0;
+    const bool job_end = ++c_t == Cq.T;
+    const bool rec_end = job_end && c_al + S >= nx;
+    if (job_end) c_t = 0;
+    // the next k-step's B, unless the group changes (its buffer is then
+    // published by the barrier below)
+    if (!rec_end) read_b();
+    if (job_end) {
       const float *fl = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c_al * RP + c;
       float fv[NT];
 #pragma unroll
@@ -619,7 +627,7 @@ __global__ void __launch_bounds__(64 * S, 1)
         __builtin_amdgcn_sched_barrier(0);
       }
       c_al += S;
-      if (c_al >= nx) {
+      if (rec_end) {
         c_al = w;
         if (Cq.last) flush(Cq, cpar);
         if (++cr == r_end) {
@@ -629,6 +637,7 @@ __global__ void __launch_bounds__(64 * S, 1)
           cpar ^= 1;
           wait_vmcnt<2 * W - 2>();
           lds_barrier();
+          read_b();
         }
       }
     }
@@ -640,6 +649,7 @@ __global__ void __launch_bounds__(64 * S, 1)
   for (int i = 0; i < W; ++i) refill(a0[i], a1[i]);
   wait_vmcnt<2 * W>();
   lds_barrier();
+  read_b();
   // The loop leaves only at the end of the unrolled body (steps after the
   // last one consume nothing and refill from the zero page): an exit from
   // inside the body would be routed through the loop latch by the control
