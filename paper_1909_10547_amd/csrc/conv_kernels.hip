@@ -871,8 +871,8 @@ __device__ __forceinline__ void had_adj_tile(const u32x4 (&a)[kTMax], int T,
   }
 }
 
-template <int DT, int NT>
-__global__ void __launch_bounds__(kThreads)
+template <int DT, int NT, int S>
+__global__ void __launch_bounds__(64 * S)
     had_adj_kernel(const HadAdjItem *__restrict__ items, const SegRef *__restrict__ segs,
                    const GroupDesc *__restrict__ gd, const u32x4 *__restrict__ bop,
                    const float *__restrict__ gout, const float *__restrict__ scale_all, int R,
@@ -886,10 +886,13 @@ __global__ void __launch_bounds__(kThreads)
   u32x4 *lb = lds;
   float *gacc = (float *)(lds + 4 * T * RP);  // [nx][RP]
   float *wl = gacc + nx * RP;                  // [16][RP]
-  copy_b(lb, bop + gd[sr.gdesc].bop_off, 4 * T * RP);
-  for (int i = threadIdx.x; i < nx * RP; i += kThreads) gacc[i] = 0.f;
+  constexpr int NTHR = 64 * S;
+  {
+    const u32x4 *src = bop + gd[sr.gdesc].bop_off;
+    for (int i = threadIdx.x; i < 4 * T * RP; i += NTHR) lb[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < nx * RP; i += NTHR) gacc[i] = 0.f;
   u32x4 a0[kTMax], a1[kTMax];
-  constexpr int S = kWaves;
   for (int bl = it.block0; bl < it.block1; ++bl) {
     const int nv = min(16, it.ndata - 16 * bl);
     const u32x4 *blk = (const u32x4 *)sr.base + (size_t)bl * nx * KE * 16;
@@ -900,7 +903,7 @@ __global__ void __launch_bounds__(kThreads)
     fetch(a0, w);
     fetch(a1, w + S);
     __syncthreads();
-    for (int i = threadIdx.x; i < 16 * RP; i += kThreads) {
+    for (int i = threadIdx.x; i < 16 * RP; i += NTHR) {
       const int row = i / RP, col = i - row * RP;
       float v = 0.f;
       if (row < nv && col < ncols) {
@@ -919,7 +922,7 @@ __global__ void __launch_bounds__(kThreads)
   }
   __syncthreads();
   float *dst = apart + (size_t)it.slot * nx * kRpMax;
-  for (int i = threadIdx.x; i < nx * RP; i += kThreads) {
+  for (int i = threadIdx.x; i < nx * RP; i += NTHR) {
     const int row = i / RP, col = i - row * RP;
     dst[row * kRpMax + col] = gacc[i];
   }
@@ -1187,9 +1190,9 @@ hipError_t launch_had_adj(const ConvLaunch &L, const HadAdjItem *items, int nite
   hipError_t err = hipSuccess;
 #define FK_HA(NT)                                                                              \
   {                                                                                            \
-    auto k = had_adj_kernel<DTV, NT>;                                                          \
+    auto k = had_adj_kernel<DTV, NT, kAdjWaves>;                                               \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                     \
-    hipLaunchKernelGGL(k, dim3(nitems), dim3(kThreads), lds, L.stream, items, segs, gd,        \
+    hipLaunchKernelGGL(k, dim3(nitems), dim3(64 * kAdjWaves), lds, L.stream, items, segs, gd,  \
                        (const u32x4 *)bop, gout, scale_all, L.R, L.c0, L.ncols, nx, apart,     \
                        (const u32x4 *)L.zero_page);                                            \
   }

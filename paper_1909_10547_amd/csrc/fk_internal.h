@@ -84,6 +84,7 @@ struct StreamSeg {
   int32_t slot;       // first partial slot of the item
   int32_t pad;
 };
+constexpr int kAdjWaves = 8;      // waves per workgroup of the hadronic adjoint (x split 8 ways)
 constexpr int kStreamW = 8;       // k-steps in flight per wave in the stream kernel
 constexpr int kStreamWaves = 8;   // waves per workgroup of the stream kernel (2 per SIMD)
 
