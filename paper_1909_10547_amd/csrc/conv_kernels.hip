@@ -217,21 +217,34 @@ __global__ void __launch_bounds__(kThreads)
   }
   const GroupDesc *G = gd + blockIdx.y;
   const int KEpad = ((G->KE + 3) >> 2) << 2;
-  if (idx >= KEpad * RP) return;
+  if ((int)blockIdx.x * kThreads >= KEpad * RP) return;  // whole block past the end
+  // the descriptor's segments in LDS: start of each segment in k, and its row
+  __shared__ int s_row[kMaxSeg], s_start[kMaxSeg + 1];
   const int nseg = G->nseg, K = G->K, src_kind = G->src;
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < nseg; ++q) {
+      s_row[q] = G->seg_row[q];
+      s_start[q] = acc;
+      acc += G->seg_len[q];
+    }
+    s_start[nseg] = acc;
+  }
+  __syncthreads();
+  if (idx >= KEpad * RP) return;
   const float *src = src_kind == 0 ? pdf : gout;
   const int u = idx / RP, n = idx - u * RP;
   // segment of the unit's first element, then walk forward
-  int s = 0, start = 0;
-  while (s < nseg - 1 && start + G->seg_len[s] <= u * E) start += G->seg_len[s++];
+  int s = 0;
+  while (s < nseg - 1 && s_start[s + 1] <= u * E) ++s;
   float v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = u * E + e;
     float x = 0.f;
     if (k < K && n < ncols) {
-      while (start + G->seg_len[s] <= k) start += G->seg_len[s++];
-      const int row = G->seg_row[s] + (k - start);
+      while (s_start[s + 1] <= k) ++s;
+      const int row = s_row[s] + (k - s_start[s]);
       x = src[(size_t)row * R + c0 + n];
       if (src_kind == 1) x *= scale_all[row];
     }
@@ -350,8 +363,9 @@ __global__ void __launch_bounds__(kThreads)
         p.KE = sr.KE;
         p.nv0 = nv0;
         p.nv1 = nv1;
-        p.p0 = base + ((size_t)bl0 * nx * 16 + (size_t)al * nv0) * sr.KE;
-        p.p1 = nv1 ? base + ((size_t)(bl0 + 1) * nx * 16 + (size_t)al * nv1) * sr.KE : zp;
+        // [pair][alpha][block of the pair][unit][row] (see the packer)
+        p.p0 = base + ((size_t)bl0 * nx * 16 + (size_t)al * (nv0 + nv1)) * sr.KE;
+        p.p1 = nv1 ? p.p0 + (size_t)nv0 * sr.KE : zp;
         p.frow = pdf + ((size_t)gd[sr.gdesc].a * nx + al) * R + c0;
       }
       return p;
@@ -508,8 +522,9 @@ __global__ void __launch_bounds__(64 * S, 1)
   int rr = r_begin, r_al = w, r_t = 0, rpar = 0;
   bool r_done = false;
   StreamSeg Rq = recs[rr];
-  gu32x4_ptr pa0 = as_global(Rq.a0) + (size_t)r_al * Rq.nv0 * Rq.KE;
-  gu32x4_ptr pa1 = as_global(Rq.a1) + (size_t)r_al * Rq.nv1 * Rq.KE;
+  // the two tiles of a pair alternate at every alpha (see the packer)
+  gu32x4_ptr pa0 = as_global(Rq.a0) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
+  gu32x4_ptr pa1 = as_global(Rq.a1) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
   // Two loads per call on every path (past the end of the list, of the zero
   // page); the cursor advance has no loads.
   auto refill = [&](u32x4 &x0, u32x4 &x1) {
@@ -535,8 +550,8 @@ __global__ void __launch_bounds__(64 * S, 1)
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        pa0 = as_global(Rq.a0) + (size_t)r_al * Rq.nv0 * Rq.KE;
-        pa1 = as_global(Rq.a1) + (size_t)r_al * Rq.nv1 * Rq.KE;
+        pa0 = as_global(Rq.a0) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
+        pa1 = as_global(Rq.a1) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
       }
     }
   };

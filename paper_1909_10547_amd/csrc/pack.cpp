@@ -333,9 +333,18 @@ void pack_had(const double *fk, const uint8_t *mask, int N, int F, int X, int dt
       }
       parallel_for(nblk, [&](int bl) {
         const int nv = std::min(16, N - 16 * bl);
-        uint8_t *bbase = buf.data() + (g.base + (size_t)bl * X * g.KE * 16) * 16;
+        // Forward copy: the two blocks of a pair (2p, 2p+1) alternate at
+        // every x index, [pair][alpha][block of the pair][unit][row], so the
+        // waves that sweep alpha together read one contiguous window.  The
+        // adjoint copy keeps [block][alpha][unit][row].
+        const int b0 = upper ? bl & ~1 : bl;
+        const int nv0 = std::min(16, N - 16 * b0);
+        const int nv1 = upper && b0 + 1 < nblk ? std::min(16, N - 16 * (b0 + 1)) : 0;
+        const size_t astride = upper ? (size_t)g.KE * (nv0 + nv1) : (size_t)g.KE * nv;
+        const size_t toff = upper && bl != b0 ? (size_t)g.KE * nv0 : 0;
+        uint8_t *bbase = buf.data() + (g.base + (size_t)b0 * X * g.KE * 16 + toff) * 16;
         for (int al = 0; al < X; ++al) {
-          uint8_t *abase = bbase + (size_t)al * g.KE * nv * 16;
+          uint8_t *abase = bbase + al * astride * 16;
           for (int u = 0; u < g.KE; ++u)
             for (int r = 0; r < nv; ++r) {
               const int i = 16 * bl + r;

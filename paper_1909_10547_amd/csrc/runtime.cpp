@@ -278,7 +278,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
             StreamSeg r;
             std::memset(&r, 0, sizeof r);
             r.a0 = sr.base + (size_t)it.block0 * X * 16 * sr.KE;
-            r.a1 = nv1 ? sr.base + (size_t)(it.block0 + 1) * X * 16 * sr.KE : nullptr;
+            r.a1 = nv1 ? r.a0 + (size_t)nv0 * sr.KE : nullptr;
             r.nv0 = nv0;
             r.nv1 = nv1;
             r.KE = sr.KE;
