@@ -3,6 +3,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -104,6 +105,61 @@ static fk_status upload(fk_ctx *c, Plan &p, const std::vector<T> &v, T **dst) {
   return FK_OK;
 }
 
+// Lower the largest load of a static partition by local search: move an
+// item of the most loaded list to a list where it ends below that load, or
+// else swap it for a smaller item of another list, taking the exchange that
+// leaves the smaller of the two new loads.  Which list runs an item does not
+// change any result (each item writes its own partial slots).
+static void rebalance(std::vector<std::vector<int>> &lists, std::vector<double> &load,
+                      const std::vector<double> &cost) {
+  const int G = (int)lists.size();
+  for (int iter = 0; iter < 4 * G; ++iter) {
+    const int mx = (int)(std::max_element(load.begin(), load.end()) - load.begin());
+    const double M = load[mx];
+    int best_j = -1, best_i = -1, best_k = -1;
+    double best = M;
+    for (int ii = 0; ii < (int)lists[mx].size(); ++ii) {
+      const double ci = cost[lists[mx][ii]];
+      for (int j = 0; j < G; ++j) {
+        if (j == mx) continue;
+        // move
+        const double mv = std::max(M - ci, load[j] + ci);
+        if (mv < best - 1e-9) {
+          best = mv;
+          best_j = j, best_i = ii, best_k = -1;
+        }
+        // swap with a smaller item of list j
+        for (int kk = 0; kk < (int)lists[j].size(); ++kk) {
+          const double ck = cost[lists[j][kk]];
+          if (ck >= ci) continue;
+          const double sw = std::max(M - ci + ck, load[j] + ci - ck);
+          if (sw < best - 1e-9) {
+            best = sw;
+            best_j = j, best_i = ii, best_k = kk;
+          }
+        }
+      }
+    }
+    if (best_j < 0) break;
+    const int item = lists[mx][best_i];
+    if (best_k < 0) {
+      lists[mx].erase(lists[mx].begin() + best_i);
+      lists[best_j].push_back(item);
+      load[mx] -= cost[item];
+      load[best_j] += cost[item];
+    } else {
+      const int other = lists[best_j][best_k];
+      lists[mx][best_i] = other;
+      lists[best_j][best_k] = item;
+      load[mx] += cost[other] - cost[item];
+      load[best_j] += cost[item] - cost[other];
+    }
+  }
+  // longest items first in every list
+  for (auto &l : lists)
+    std::stable_sort(l.begin(), l.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+}
+
 static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) {
   const bool had = p.kind == FK_HAD;
   const int X = p.X, F = p.F;
@@ -111,8 +167,22 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   std::vector<SegRef> segs;
   std::vector<std::vector<int>> segidx(ts.size());
   size_t bop = 0;
+  // Descriptors that gather the same PDF rows (tables with the same flavour
+  // pattern have the same groups) share one staged B operand, so a group
+  // launch stages, and the forward kernels read, each distinct operand once.
+  // Sharing stays within one phase (forward or adjoint), whose descriptors
+  // the stage kernel walks as one contiguous range.
+  std::map<std::vector<int>, int> same_b;
   auto add_gd = [&](int a, int src, const std::vector<int> &rows, const std::vector<int> &lens,
                     int K, int KE) {
+    std::vector<int> key;
+    if (src == 0) {
+      key = {a, K, KE, (int)rows.size()};
+      key.insert(key.end(), rows.begin(), rows.end());
+      key.insert(key.end(), lens.begin(), lens.end());
+      auto it = same_b.find(key);
+      if (it != same_b.end()) return it->second;
+    }
     GroupDesc d;
     std::memset(&d, 0, sizeof d);
     d.a = a;
@@ -127,6 +197,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     }
     bop += (size_t)((KE + 3) / 4) * 4 * kRpMax;
     gd.push_back(d);
+    if (src == 0) same_b[key] = (int)gd.size() - 1;
     return (int)gd.size() - 1;
   };
   p.row0.clear();
@@ -149,6 +220,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
       p.maxT_fwd = std::max(p.maxT_fwd, (g.KE + 3) / 4);
     }
   p.ngd_fwd = (int)gd.size();
+  same_b.clear();
   std::vector<std::vector<int>> chunkgd(ts.size()), asegidx(ts.size());
   if (!had)
     for (size_t t = 0; t < ts.size(); ++t)
@@ -258,15 +330,22 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
         return x.first != y.first ? x.first > y.first : x.second > y.second;
       };
       std::make_heap(heap.begin(), heap.end(), cmp);
+      // cost in k-steps of the busiest wave: T per job, ceil(X/8) jobs per
+      // record, about five k-steps per group change and eight per item for
+      // the combine and write of its partial sums
+      std::vector<double> icost(items.size()), load(G, 0.0);
       for (size_t k = 0; k < items.size(); ++k) {
-        double cost = 16.0;  // combine and write of the item's partial sums
+        double cost = 8.0;
         for (int sg = items[k].seg0; sg < items[k].seg1; ++sg)
-          cost += (double)((segs[sg].KE + 3) / 4) * nal + 4.0;
+          cost += (double)((segs[sg].KE + 3) / 4) * nal + 5.0;
+        icost[k] = cost;
         std::pop_heap(heap.begin(), heap.end(), cmp);
         lists[heap.back().second].push_back((int)k);
         heap.back().first += cost;
+        load[heap.back().second] += cost;
         std::push_heap(heap.begin(), heap.end(), cmp);
       }
+      rebalance(lists, load, icost);
       wgptr.push_back(0);
       for (int g = 0; g < G; ++g) {
         for (int k : lists[g]) {
@@ -512,7 +591,7 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
     if (e != hipSuccess) return e;
     if (dstream) {
       // the DIS stream kernel writes the output rows itself
-      e = timed(tm, FK_K_DIS_FWD, s, [&] {
+      e = timed(tm, FK_K_DIS_STREAM, s, [&] {
         return launch_dis_stream(L, p.d_dwgs, p.n_dwgs, p.d_dgroups, p.d_bop, p.d_scale,
                                  p.dis_ttot_max, out);
       });
@@ -520,7 +599,7 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
       continue;
     }
     if (stream)
-      e = timed(tm, FK_K_HAD_FWD, s, [&] {
+      e = timed(tm, FK_K_HAD_STREAM, s, [&] {
         return launch_had_stream(L, p.d_srec, p.d_wgptr, p.grid_stream, p.d_bop, p.d_fstage, p.X,
                                  p.maxT_fwd, p.d_fpart);
       });

@@ -196,6 +196,45 @@ def test_groups_concatenate_datasets(ctx):
             fkconv.fk_unload_table(ctx.ctx, h)
 
 
+@pytest.mark.parametrize("kind", ["had", "dis"])
+def test_groups_of_tables_with_one_flavour_pattern(ctx, kind):
+    """Tables with the same active flavours share their staged B operands
+    inside a group; each member's rows stay bitwise its result alone."""
+    if kind == "had":
+        w = synth.had_fit_workload(scale=0.03)
+        t0 = w.table(0)
+        mk = lambda fk: synth.HadTable(mask=t0.mask, fk=fk, xgrid=t0.xgrid)
+    else:
+        w = synth.dis_fit_workload(scale=0.05)
+        t0 = w.table(0)
+        mk = lambda fk: synth.DisTable(mask=t0.mask, fk=fk, xgrid=t0.xgrid)
+    # same pattern, other values and sizes: reversed datapoints, a scaled
+    # prefix, and the original
+    tabs = [t0, mk(np.ascontiguousarray(t0.fk[::-1] * 0.5)), mk(np.ascontiguousarray(t0.fk[:7] * -2.0))]
+    pdf32 = f32(w.pdf(16))
+    fn = oracle.had if kind == "had" else oracle.dis
+    for fmt in ("f32", "bf16"):
+        hs = [ctx.load(t, fmt) for t in tabs]
+        g = fkconv.fk_group_create(ctx.ctx, hs)
+        got = run_conv(ctx, g, kind, pdf32)
+        ref = np.concatenate([fn(t.mask, t.fk, pdf32) for t in tabs])
+        e = oracle.normwise_rel(got, ref)
+        say(f"{kind} group with one flavour pattern {fmt}: {e:.3e}")
+        if fmt == "f32":
+            assert e <= TOL64[fmt]
+        else:
+            qf = oracle.had_quantized if kind == "had" else oracle.dis_quantized
+            q = np.concatenate([qf(t.mask, t.fk, pdf32, fmt) for t in tabs])
+            assert oracle.normwise_rel(got, q) <= TOLQ[fmt]
+        off = 0
+        for h, t in zip(hs, tabs):
+            np.testing.assert_array_equal(run_conv(ctx, h, kind, pdf32), got[off:off + t.ndata])
+            off += t.ndata
+        fkconv.fk_unload_table(ctx.ctx, g)
+        for h in hs:
+            fkconv.fk_unload_table(ctx.ctx, h)
+
+
 def test_deterministic(ctx):
     w = synth.had_fit_workload(scale=0.05)
     tab = w.table(2)

@@ -116,3 +116,45 @@ def test_dis_stream_against_partial_sum_kernel_and_oracle(fmt, R):
         e = float(np.max(np.abs(y.double().cpu().numpy() - q) / np.where(absterms > 0, absterms, 1.0)))
         say(f"  {name}: stored-operand error {e:.2e} of sum|terms|")
         assert e <= tol, name
+
+
+def test_timing_kinds_name_the_kernel_that_ran():
+    """Kernel timing books the stream kernels under their own kinds, so a
+    timing read says which forward kernel a call used."""
+    w = synth.had_fit_workload(scale=0.05)
+    t = w.table(0)
+    wd = synth.dis_fit_workload(scale=0.05)
+    td = wd.table(0)
+    R = 16
+    with fkconv.Context(0) as c:
+        h = c.load(t, "bf16")
+        hd = c.load(td, "bf16")
+        x = torch.from_numpy(w.pdf(R).astype(np.float32)).cuda()
+        xd = torch.from_numpy(wd.pdf(R).astype(np.float32)).cuda()
+        for stream in (True, False):
+            if stream:
+                os.environ.pop("FKCONV_NO_STREAM", None)
+            else:
+                os.environ["FKCONV_NO_STREAM"] = "1"
+            try:
+                fkconv.fk_timing_read(c.ctx)
+                fkconv.fk_timing_enable(c.ctx, True)
+                fkconv.fk_conv_had(c.ctx, h, x)
+                fkconv.fk_conv_dis(c.ctx, hd, xd)
+                torch.cuda.synchronize()
+                fkconv.fk_timing_enable(c.ctx, False)
+                kt = fkconv.fk_timing_read(c.ctx)
+            finally:
+                os.environ.pop("FKCONV_NO_STREAM", None)
+            say(f"stream={stream}: {({k: v[1] for k, v in kt.items() if v[1]})}")
+            assert kt["stage"][1] == 2
+            if stream:
+                assert kt["had_stream"][1] == 1 and kt["had_fwd"][1] == 0
+                assert kt["dis_stream"][1] == 1 and kt["dis_fwd"][1] == 0
+                assert kt["fwd_reduce"][1] == 1  # the hadronic items' partial sums
+            else:
+                assert kt["had_fwd"][1] == 1 and kt["had_stream"][1] == 0
+                assert kt["dis_fwd"][1] == 1 and kt["dis_stream"][1] == 0
+                assert kt["fwd_reduce"][1] == 2
+        fkconv.fk_unload_table(c.ctx, h)
+        fkconv.fk_unload_table(c.ctx, hd)
