@@ -111,8 +111,8 @@ def fwd_kernel(kt, kind):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--scale", type=float, default=1.0,
                     help="shrink dataset sizes (quick checks only; the metric uses 1.0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -197,10 +197,10 @@ __device__ __forceinline__ u32x4 pack_unit<FK_FP8E4M3>(const float *v) {
 // ---------------------------------------------------------------------------
 template <int DT>
 __global__ void __launch_bounds__(kThreads)
-    stage_b_kernel(const GroupDesc *__restrict__ gd, int ngd, const float *__restrict__ pdf,
-                   const float *__restrict__ gout, const float *__restrict__ scale_all, int R,
-                   int c0, int ncols, int RP, u32x4 *__restrict__ bop, int *counter,
-                   float *__restrict__ fstage, int nx) {
+    stage_b_kernel(const GroupDesc *__restrict__ gd, const int32_t *__restrict__ rowtab, int ngd,
+                   const float *__restrict__ pdf, const float *__restrict__ gout,
+                   const float *__restrict__ scale_all, int R, int c0, int ncols, int RP,
+                   u32x4 *__restrict__ bop, int *counter, float *__restrict__ fstage, int nx) {
   constexpr int E = Mma<DT>::E;
   // the forward kernel that follows on the stream takes items from *counter
   if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;
@@ -217,36 +217,29 @@ __global__ void __launch_bounds__(kThreads)
   }
   const GroupDesc *G = gd + blockIdx.y;
   const int KEpad = ((G->KE + 3) >> 2) << 2;
-  if ((int)blockIdx.x * kThreads >= KEpad * RP) return;  // whole block past the end
-  // the descriptor's segments in LDS: start of each segment in k, and its row
-  __shared__ int s_row[kMaxSeg], s_start[kMaxSeg + 1];
-  const int nseg = G->nseg, K = G->K, src_kind = G->src;
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int q = 0; q < nseg; ++q) {
-      s_row[q] = G->seg_row[q];
-      s_start[q] = acc;
-      acc += G->seg_len[q];
-    }
-    s_start[nseg] = acc;
-  }
-  __syncthreads();
   if (idx >= KEpad * RP) return;
+  const int src_kind = G->src;
   const float *src = src_kind == 0 ? pdf : gout;
   const int u = idx / RP, n = idx - u * RP;
-  // segment of the unit's first element, then walk forward
-  int s = 0;
-  while (s < nseg - 1 && s_start[s + 1] <= u * E) ++s;
+  // the unit's E source rows (-1 past the contraction length), read as
+  // 16-byte vectors: every thread of a unit reads the same ones
+  int row[E];
+  const int32_t *rp = rowtab + G->row_off + (size_t)u * E;
+#pragma unroll
+  for (int q = 0; q < E / 4; ++q) {
+    const int4 r4 = *(const int4 *)(rp + 4 * q);
+    row[4 * q] = r4.x;
+    row[4 * q + 1] = r4.y;
+    row[4 * q + 2] = r4.z;
+    row[4 * q + 3] = r4.w;
+  }
   float v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int k = u * E + e;
     float x = 0.f;
-    if (k < K && n < ncols) {
-      while (s_start[s + 1] <= k) ++s;
-      const int row = s_row[s] + (k - s_start[s]);
-      x = src[(size_t)row * R + c0 + n];
-      if (src_kind == 1) x *= scale_all[row];
+    if (row[e] >= 0 && n < ncols) {
+      x = src[(size_t)row[e] * R + c0 + n];
+      if (src_kind == 1) x *= scale_all[row[e]];
     }
     v[e] = x;
   }
@@ -978,29 +971,40 @@ __global__ void __launch_bounds__(kThreads)
 // ---------------------------------------------------------------------------
 // Reductions in a fixed order
 // ---------------------------------------------------------------------------
+template <int V>
 __global__ void __launch_bounds__(kThreads)
     fwd_reduce_kernel(const RedBlock *__restrict__ blocks, const int32_t *__restrict__ slot_idx,
                       const float *__restrict__ part, const float *__restrict__ scale_all,
                       float factor, int R, int c0, int ncols, float *__restrict__ out) {
-  // grid: x = chunk of kThreads outputs of the block, y = output block
+  // grid: x = chunk of kThreads groups of V adjacent outputs of the block,
+  // y = output block.  V = 4 needs ncols, R and c0 multiples of 4 (and an
+  // aligned output): then every access is 16 bytes wide.  Each output is
+  // the same sum either way: its slots in list order.
+  typedef float vec __attribute__((ext_vector_type(V)));
   const RedBlock b = blocks[blockIdx.y];
+  const int nc = ncols / V;
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= b.nv * ncols) return;
-  const int row = i / ncols, col = i - row * ncols;
+  if (i >= b.nv * nc) return;
+  const int row = i / nc, col = (i - row * nc) * V;
   const float *p = part + row * kRpMax + col;
-  // slots in list order; the loads of eight slots are issued together
-  float acc = 0.f;
-  int k = b.k0;
-  for (; k + 8 <= b.k1; k += 8) {
-    float v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = p[(size_t)slot_idx[k + q] * 16 * kRpMax];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc += v[q];
-  }
-  for (; k < b.k1; ++k) acc += p[(size_t)slot_idx[k] * 16 * kRpMax];
+  auto at = [&](int slot) { return *(const vec *)(p + (size_t)slot * 16 * kRpMax); };
   const int orow = b.orow + row;
-  out[(size_t)orow * R + c0 + col] = factor * scale_all[orow] * acc;
+  const float sc = factor * scale_all[orow];
+  const int n = b.k1 - b.k0;
+  vec acc = vec(0.f);
+  if (n > 0) {
+    // the first slots are held in the block record itself; their loads are
+    // issued together, unconditionally (past the block's count they re-read
+    // its first slot and are not added)
+    const int ni = n < kRedInline ? n : kRedInline;
+    vec v[kRedInline];
+#pragma unroll
+    for (int q = 0; q < kRedInline; ++q) v[q] = at(q < ni ? b.slot[q] : b.slot[0]);
+#pragma unroll
+    for (int q = 0; q < kRedInline; ++q) acc = q < ni ? acc + v[q] : acc;
+    for (int k = b.k0 + ni; k < b.k1; ++k) acc += at(slot_idx[k]);
+  }
+  *(vec *)(out + (size_t)orow * R + c0 + col) = sc * acc;
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -1050,7 +1054,8 @@ hipError_t set_lds(KernT kern, size_t bytes) {
 
 }  // namespace
 
-hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
+hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, const int32_t *rowtab,
+                          int ngd, const float *pdf,
                           const float *gout, const float *scale_all, uint4 *bop, int *counter,
                           float *fstage, int nflav, int nx) {
   if (ngd <= 0) return hipSuccess;
@@ -1061,9 +1066,9 @@ hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, c
   if (fstage) units = std::max(units, nx * RP);
   const dim3 grid((units + kThreads - 1) / kThreads, rows);
 #define FK_STAGE(DT)                                                                          \
-  hipLaunchKernelGGL(stage_b_kernel<DT>, grid, dim3(kThreads), 0, L.stream, d_gd, ngd, pdf,   \
-                     gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop, counter, fstage,  \
-                     nx)
+  hipLaunchKernelGGL(stage_b_kernel<DT>, grid, dim3(kThreads), 0, L.stream, d_gd, rowtab, ngd, \
+                     pdf, gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop, counter,      \
+                     fstage, nx)
   FK_DISPATCH_DT(FK_STAGE);
 #undef FK_STAGE
   return hipGetLastError();
@@ -1189,9 +1194,16 @@ hipError_t launch_fwd_reduce(const ConvLaunch &L, const RedBlock *blocks, int nb
                              const int32_t *slot_idx, const float *part, const float *scale_all,
                              float factor, float *out) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((16 * L.ncols + kThreads - 1) / kThreads, nblocks),
-                     dim3(kThreads), 0, L.stream, blocks,
-                     slot_idx, part, scale_all, factor, L.R, L.c0, L.ncols, out);
+  const bool v4 = L.ncols % 4 == 0 && L.R % 4 == 0 && L.c0 % 4 == 0 && (uintptr_t)out % 16 == 0;
+  if (v4)
+    hipLaunchKernelGGL(fwd_reduce_kernel<4>,
+                       dim3((16 * L.ncols / 4 + kThreads - 1) / kThreads, nblocks), dim3(kThreads),
+                       0, L.stream, blocks, slot_idx, part, scale_all, factor, L.R, L.c0, L.ncols,
+                       out);
+  else
+    hipLaunchKernelGGL(fwd_reduce_kernel<1>, dim3((16 * L.ncols + kThreads - 1) / kThreads, nblocks),
+                       dim3(kThreads), 0, L.stream, blocks, slot_idx, part, scale_all, factor, L.R,
+                       L.c0, L.ncols, out);
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ struct GroupDesc {
   int32_t KE;       // units per row = ceil(K / E)
   int32_t pad;
   int64_t bop_off;  // offset of the staged B operand, in 16-byte units
+  int64_t row_off;  // offset of its gather rows: KEpad*E source rows, -1 past K
   int32_t seg_row[kMaxSeg];
   int32_t seg_len[kMaxSeg];
 };
@@ -131,10 +132,12 @@ struct DisAdjItem {
 };
 
 // Forward reduction of one output block of 16 datapoints.
+constexpr int kRedInline = 8;  // slots of an output block held in its record
 struct RedBlock {
   int32_t orow;     // first output row
   int32_t nv;       // rows in the block
   int32_t k0, k1;   // range in the slot index list
+  int32_t slot[kRedInline];  // slot_idx[k0 .. k0 + kRedInline), where present
 };
 
 // ---------------------------------------------------------------------------
@@ -149,7 +152,8 @@ struct ConvLaunch {
 };
 constexpr int kZeroPageBytes = 4096;
 
-hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, int ngd, const float *pdf,
+hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, const int32_t *rowtab,
+                          int ngd, const float *pdf,
                           const float *gout, const float *scale_all, uint4 *bop, int *counter,
                           float *fstage = nullptr, int nflav = 0, int nx = 0);
 // LDS of the stream kernel for (nt, nx, maxT); 0 when it does not fit.

@@ -173,6 +173,8 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   // Sharing stays within one phase (forward or adjoint), whose descriptors
   // the stage kernel walks as one contiguous range.
   std::map<std::vector<int>, int> same_b;
+  std::vector<int32_t> rowtab;
+  const int E = elems_per_unit(p.dtype);
   auto add_gd = [&](int a, int src, const std::vector<int> &rows, const std::vector<int> &lens,
                     int K, int KE) {
     std::vector<int> key;
@@ -185,6 +187,12 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     }
     GroupDesc d;
     std::memset(&d, 0, sizeof d);
+    // source row of every staged element, in k order: the segments
+    // concatenated, -1 from K up to the whole k-step (KEpad units)
+    d.row_off = (int64_t)rowtab.size();
+    for (size_t q = 0; q < rows.size(); ++q)
+      for (int e = 0; e < lens[q]; ++e) rowtab.push_back(rows[q] + e);
+    rowtab.resize((size_t)d.row_off + (size_t)((KE + 3) / 4) * 4 * E, -1);
     d.a = a;
     d.src = src;
     d.nseg = (int)rows.size();
@@ -278,11 +286,13 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     }
     for (int bl = 0; bl < nblk; ++bl) {
       RedBlock rb;
+      std::memset(&rb, 0, sizeof rb);
       rb.orow = p.row0[t] + 16 * bl;
       rb.nv = std::min(16, T->N - 16 * bl);
       rb.k0 = (int)slot_idx.size();
       slot_idx.insert(slot_idx.end(), bslots[bl].begin(), bslots[bl].end());
       rb.k1 = (int)slot_idx.size();
+      for (int q = 0; q < kRedInline && rb.k0 + q < rb.k1; ++q) rb.slot[q] = slot_idx[rb.k0 + q];
       rblocks.push_back(rb);
     }
   }
@@ -495,6 +505,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
 
   fk_status st;
   if ((st = upload(c, p, gd, &p.d_gd))) return st;
+  if ((st = upload(c, p, rowtab, &p.d_rowtab))) return st;
   if ((st = upload(c, p, segs, &p.d_seg))) return st;
   if ((st = upload(c, p, items, &p.d_fitems))) return st;
   if ((st = upload(c, p, rblocks, &p.d_rblocks))) return st;
@@ -585,7 +596,7 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
     ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
     hipError_t e = timed(tm, FK_K_STAGE, s, [&] {
-      return launch_stage_b(L, p.d_gd, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, p.d_counter,
+      return launch_stage_b(L, p.d_gd, p.d_rowtab, p.ngd_fwd, pdf, nullptr, p.d_scale, p.d_bop, p.d_counter,
                             stream ? p.d_fstage : nullptr, p.F, p.X);
     });
     if (e != hipSuccess) return e;
@@ -632,7 +643,7 @@ hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int 
     hipError_t e;
     if (p.kind == FK_HAD) {
       e = timed(tm, FK_K_STAGE, s, [&] {
-        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.ngd_adj, pdf, nullptr, p.d_scale, p.d_bop,
+        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.d_rowtab, p.ngd_adj, pdf, nullptr, p.d_scale, p.d_bop,
                               nullptr);
       });
       if (e != hipSuccess) return e;
@@ -642,7 +653,7 @@ hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int 
       });
     } else {
       e = timed(tm, FK_K_STAGE, s, [&] {
-        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.ngd_adj, nullptr, gout, p.d_scale,
+        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.d_rowtab, p.ngd_adj, nullptr, gout, p.d_scale,
                               p.d_bop, nullptr);
       });
       if (e != hipSuccess) return e;

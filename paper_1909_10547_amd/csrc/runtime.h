@@ -43,6 +43,7 @@ struct Plan {
   std::vector<int> row0;
   // device descriptors
   GroupDesc *d_gd = nullptr;
+  int32_t *d_rowtab = nullptr;  // gather rows of the descriptors (GroupDesc::row_off)
   int ngd_fwd = 0, ngd_adj = 0;  // forward descriptors, then adjoint-only ones
   SegRef *d_seg = nullptr;
   FwdItem *d_fitems = nullptr;
