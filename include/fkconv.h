@@ -189,13 +189,14 @@ enum {
   FK_K_HAD_FWD = 1,     /* hadronic forward MFMA kernel, persistent form */
   FK_K_DIS_FWD = 2,     /* DIS forward MFMA kernel, partial-sum form */
   FK_K_FWD_REDUCE = 3,  /* forward partial-sum reduction */
-  FK_K_HAD_ADJ = 4,     /* hadronic adjoint MFMA kernel */
+  FK_K_HAD_ADJ = 4,     /* hadronic adjoint MFMA kernel, per-item form */
   FK_K_DIS_ADJ = 5,     /* DIS adjoint MFMA kernel */
   FK_K_ADJ_REDUCE = 6,  /* adjoint partial-sum reduction */
   FK_K_CHI2 = 7,        /* FP64 chi2 kernels of one call, together */
   FK_K_HAD_STREAM = 8,  /* hadronic forward MFMA kernel, stream form */
   FK_K_DIS_STREAM = 9,  /* DIS forward MFMA kernel, stream form (no reduction) */
-  FK_K_COUNT = 10
+  FK_K_HAD_ADJ_STREAM = 10, /* hadronic adjoint MFMA kernel, stream form */
+  FK_K_COUNT = 11
 };
 fk_status fk_timing_enable(fk_ctx *ctx, int32_t enable);
 

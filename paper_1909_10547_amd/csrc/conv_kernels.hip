@@ -200,12 +200,26 @@ __global__ void __launch_bounds__(kThreads)
     stage_b_kernel(const GroupDesc *__restrict__ gd, const int32_t *__restrict__ rowtab, int ngd,
                    const float *__restrict__ pdf, const float *__restrict__ gout,
                    const float *__restrict__ scale_all, int R, int c0, int ncols, int RP,
-                   u32x4 *__restrict__ bop, int *counter, float *__restrict__ fstage, int nx) {
+                   u32x4 *__restrict__ bop, int *counter, float *__restrict__ fstage, int nx,
+                   const int32_t *__restrict__ wrow, float *__restrict__ wstage, int nwpair) {
   constexpr int E = Mma<DT>::E;
   // the forward kernel that follows on the stream takes items from *counter
   if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;
   // grid: x = chunk of kThreads units (or floats), y = descriptor
   const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if ((int)blockIdx.y >= ngd && wstage) {
+    // rows past the descriptors: the adjoint weights gbar * s of each block
+    // pair, column by column [pair][RP][kAdjWRow], zero for columns >=
+    // ncols, padding rows and the pad of a column
+    const size_t i = (size_t)(blockIdx.y - ngd) * gridDim.x * kThreads + idx;
+    if (i >= (size_t)nwpair * RP * kAdjWRow) return;
+    const int q = (int)(i % kAdjWRow);
+    const size_t pn = i / kAdjWRow;
+    const int n = (int)(pn % RP), P = (int)(pn / RP);
+    const int r = q < 32 ? wrow[32 * P + q] : -1;
+    wstage[i] = r >= 0 && n < ncols ? gout[(size_t)r * R + c0 + n] * scale_all[r] : 0.f;
+    return;
+  }
   if ((int)blockIdx.y >= ngd) {
     // rows past the descriptors: FP32 PDF rows of flavour a for the
     // epilogue of the stream kernel, [alpha][RP], zero for columns >= ncols
@@ -479,13 +493,14 @@ __device__ __forceinline__ void dma_copy(u32x4 *dst, const u32x4 *src, int units
   }
 }
 
-template <int DT, int NT, int W, int S>
+template <int DT, int NT, int W, int S, int MODE>
 __global__ void __launch_bounds__(64 * S, 1)
     had_stream_kernel(const StreamSeg *__restrict__ recs, const int32_t *__restrict__ wg_ptr,
                       const u32x4 *__restrict__ bop, const float *__restrict__ fstage, int nx,
                       int bufsz, float *__restrict__ part, const u32x4 *zp) {
   constexpr int RP = 16 * NT;
   constexpr int NTHR = 64 * S;
+  constexpr bool ADJ = MODE == kStreamAdj;
   extern __shared__ u32x4 lds[];
   // the wave index is uniform: say so, so that every cursor below lives in
   // scalar registers and every branch on it is a scalar branch
@@ -501,23 +516,38 @@ __global__ void __launch_bounds__(64 * S, 1)
   zero(acc1);
   zero(sacc0);
   zero(sacc1);
+  // adjoint: the gradient rows of the wave's x indices alpha = w + S k; lane
+  // (g, c) keeps k = g (gr0) and k = g + 4 (gr1)
+  // (vectors, so that they stay in registers whatever the inliner does)
+  typedef float f32x8 __attribute__((ext_vector_type(8)));
+  static_assert(NT <= 8, "eight column tiles at most");
+  f32x8 gr0 = f32x8(0.f), gr1 = f32x8(0.f);
 
-  // B operand and PDF row of record ``q`` into buffer ``par``
+  // B operand of record ``q`` and its epilogue rows into buffer ``par``:
+  // forward, the FP32 PDF rows of its flavour; adjoint, the weights of its
+  // two blocks
   auto stage = [&](const StreamSeg &q, int par) {
     u32x4 *buf = lds + par * bufsz;
     const int ub = 4 * q.T * RP;
     dma_copy<S>(buf, bop + q.bop_off, ub, zp, w, lane);
-    dma_copy<S>(buf + ub, (const u32x4 *)(fstage + (size_t)q.flav * nx * RP), nx * RP / 4, zp, w,
-                lane);
+    if (ADJ)
+      dma_copy<S>(buf + ub, (const u32x4 *)(fstage + (size_t)q.flav * RP * kAdjWRow),
+                  RP * kAdjWRow / 4, zp, w, lane);
+    else
+      dma_copy<S>(buf + ub, (const u32x4 *)(fstage + (size_t)q.flav * nx * RP), nx * RP / 4, zp,
+                  w, lane);
   };
 
   // refill cursor: record rr, job alpha r_al, k-step r_t
   int rr = r_begin, r_al = w, r_t = 0, rpar = 0;
   bool r_done = false;
   StreamSeg Rq = recs[rr];
-  // the two tiles of a pair alternate at every alpha (see the packer)
-  gu32x4_ptr pa0 = as_global(Rq.a0) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
-  gu32x4_ptr pa1 = as_global(Rq.a1) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
+  // forward copy: the two tiles of a pair alternate at every alpha (see the
+  // packer); adjoint copy: each block's tiles follow one another
+  auto stride0 = [](const StreamSeg &q) { return (size_t)(ADJ ? q.nv0 : q.nv0 + q.nv1) * q.KE; };
+  auto stride1 = [](const StreamSeg &q) { return (size_t)(ADJ ? q.nv1 : q.nv0 + q.nv1) * q.KE; };
+  gu32x4_ptr pa0 = as_global(Rq.a0) + r_al * stride0(Rq);
+  gu32x4_ptr pa1 = as_global(Rq.a1) + r_al * stride1(Rq);
   // Two loads per call on every path (past the end of the list, of the zero
   // page); the cursor advance has no loads.
   auto refill = [&](u32x4 &x0, u32x4 &x1) {
@@ -543,8 +573,8 @@ __global__ void __launch_bounds__(64 * S, 1)
             __builtin_amdgcn_sched_barrier(0);
           }
         }
-        pa0 = as_global(Rq.a0) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
-        pa1 = as_global(Rq.a1) + (size_t)r_al * (Rq.nv0 + Rq.nv1) * Rq.KE;
+        pa0 = as_global(Rq.a0) + r_al * stride0(Rq);
+        pa1 = as_global(Rq.a1) + r_al * stride1(Rq);
       }
     }
   };
@@ -552,6 +582,19 @@ __global__ void __launch_bounds__(64 * S, 1)
   // The waves' sums of the item, combined in a fixed order: with eight
   // waves, wave w + 4 first adds its sums into wave w's (w < 4); then the
   // four remaining sums are added in wave order.
+  // Adjoint: the item's gradient rows go straight from the registers to its
+  // slot [x][kRpMax]; no other wave holds the same x index.
+  auto flush_adj = [&](const StreamSeg &q) {
+    float *dst = part + (size_t)q.slot * nx * kRpMax + 16 * 0 + c;
+    const int al0 = w + S * g, al1 = w + S * (g + 4);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      if (al0 < nx) dst[(size_t)al0 * kRpMax + 16 * j] = gr0[j];
+      if (al1 < nx) dst[(size_t)al1 * kRpMax + 16 * j] = gr1[j];
+    }
+    gr0 = f32x8(0.f);
+    gr1 = f32x8(0.f);
+  };
   auto flush = [&](const StreamSeg &q, int par) {
     float *red = (float *)(lds + par * bufsz);  // [block][4][16][RP]
     auto put = [&](int slot) {
@@ -598,7 +641,7 @@ __global__ void __launch_bounds__(64 * S, 1)
   // The B fragments of a k-step are read right after the MFMAs of the one
   // before (same registers), so their LDS latency overlaps the epilogue, the
   // cursor work and the refill.
-  int cr = r_begin, c_al = w, c_t = 0, cpar = 0;
+  int cr = r_begin, c_al = w, c_t = 0, cpar = 0, c_k = 0;
   StreamSeg Cq = Rq;
   bool done = false;
   u32x4 b[NT];
@@ -607,6 +650,7 @@ __global__ void __launch_bounds__(64 * S, 1)
 #pragma unroll
     for (int j = 0; j < NT; ++j) b[j] = bp[16 * j];
   };
+
   auto consume = [&](const u32x4 &x0, const u32x4 &x1) {
     if (done) return;
 #pragma unroll
@@ -621,23 +665,55 @@ __global__ void __launch_bounds__(64 * S, 1)
     // published by the barrier below)
     if (!rec_end) read_b();
     if (job_end) {
-      const float *fl = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c_al * RP + c;
-      float fv[NT];
+      if (ADJ) {
+        // sum over the 16 rows of each tile of acc times the weights (the
+        // lane's four rows are one 16-byte read of a weight column); the
+        // tile of an absent second block is skipped
+        const float *wt = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c * kAdjWRow + 4 * g;
 #pragma unroll
-      for (int j = 0; j < NT; ++j) fv[j] = fl[16 * j];
-      // one column tile at a time keeps few accumulators in flight
+        for (int j = 0; j < NT; ++j) {
+          const f32x4 w0 = *(const f32x4 *)(wt + 16 * j * kAdjWRow);
+          float v = ((acc0[j][0] * w0[0] + acc0[j][1] * w0[1]) + acc0[j][2] * w0[2]) +
+                    acc0[j][3] * w0[3];
+          if (Cq.nv1 > 0) {
+            const f32x4 w1 = *(const f32x4 *)(wt + 16 * j * kAdjWRow + 16);
+            v += ((acc1[j][0] * w1[0] + acc1[j][1] * w1[1]) + acc1[j][2] * w1[2]) +
+                 acc1[j][3] * w1[3];
+          }
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          // branch-free: both rows are updated, one of them by zero
+          gr0[j] += g == c_k ? v : 0.f;
+          gr1[j] += g == c_k - 4 ? v : 0.f;
+          acc0[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      } else {
+        const float *fl = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c_al * RP + c;
+        float fv[NT];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        sacc0[j] += acc0[j] * fv[j];
-        sacc1[j] += acc1[j] * fv[j];
-        acc0[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        __builtin_amdgcn_sched_barrier(0);
+        for (int j = 0; j < NT; ++j) fv[j] = fl[16 * j];
+        // one column tile at a time keeps few accumulators in flight
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          sacc0[j] += acc0[j] * fv[j];
+          sacc1[j] += acc1[j] * fv[j];
+          acc0[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
       c_al += S;
+      ++c_k;
       if (rec_end) {
         c_al = w;
-        if (Cq.last) flush(Cq, cpar);
+        c_k = 0;
+        if (Cq.last) {
+          if (ADJ)
+            flush_adj(Cq);
+          else
+            flush(Cq, cpar);
+        }
         if (++cr == r_end) {
           done = true;
         } else {
@@ -1057,18 +1133,24 @@ hipError_t set_lds(KernT kern, size_t bytes) {
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, const int32_t *rowtab,
                           int ngd, const float *pdf,
                           const float *gout, const float *scale_all, uint4 *bop, int *counter,
-                          float *fstage, int nflav, int nx) {
+                          float *fstage, int nflav, int nx, const int32_t *wrow, float *wstage,
+                          int nwpair) {
   if (ngd <= 0) return hipSuccess;
+  if (fstage && wstage) return hipErrorInvalidValue;
   const int RP = 16 * L.nt;
-  const int rows = ngd + (fstage ? nflav : 0);
   // one thread per staged unit (a group's B has at most 4*kTMax*RP units)
   int units = 4 * kTMax * RP;
   if (fstage) units = std::max(units, nx * RP);
-  const dim3 grid((units + kThreads - 1) / kThreads, rows);
+  const int gx = (units + kThreads - 1) / kThreads;
+  int rows = ngd + (fstage ? nflav : 0);
+  if (wstage)
+    rows += (int)(((size_t)nwpair * RP * kAdjWRow + (size_t)gx * kThreads - 1) /
+                  ((size_t)gx * kThreads));
+  const dim3 grid(gx, rows);
 #define FK_STAGE(DT)                                                                          \
   hipLaunchKernelGGL(stage_b_kernel<DT>, grid, dim3(kThreads), 0, L.stream, d_gd, rowtab, ngd, \
                      pdf, gout, scale_all, L.R, L.c0, L.ncols, RP, (u32x4 *)bop, counter,      \
-                     fstage, nx)
+                     fstage, nx, wrow, wstage, nwpair)
   FK_DISPATCH_DT(FK_STAGE);
 #undef FK_STAGE
   return hipGetLastError();
@@ -1101,10 +1183,12 @@ hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems,
   return hipGetLastError();
 }
 
-size_t had_stream_lds_bytes(int nt, int nx, int maxT) {
+size_t had_stream_lds_bytes(int nt, int nx, int maxT, int mode) {
   const int RP = 16 * nt;
-  // B operand + PDF rows, or the combine buffer [2][4][16][RP] floats
-  int units = std::max(4 * maxT * RP + nx * RP / 4, 2 * 4 * 16 * RP / 4);
+  // forward: B operand + PDF rows, or the combine buffer [2][4][16][RP]
+  // floats; adjoint: B operand + the weights [RP][kAdjWRow] floats
+  int units = mode == kStreamAdj ? 4 * maxT * RP + RP * kAdjWRow / 4
+                                 : std::max(4 * maxT * RP + nx * RP / 4, 2 * 4 * 16 * RP / 4);
   units = (units + 63) / 64 * 64;
   const size_t bytes = (size_t)2 * units * 16;
   return bytes <= 163840 ? bytes : 0;
@@ -1112,18 +1196,26 @@ size_t had_stream_lds_bytes(int nt, int nx, int maxT) {
 
 hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const int32_t *wg_ptr,
                              int grid, const uint4 *bop, const float *fstage, int nx, int maxT,
-                             float *part) {
+                             float *part, int mode) {
   if (grid <= 0) return hipSuccess;
-  const size_t lds = had_stream_lds_bytes(L.nt, nx, maxT);
+  const size_t lds = had_stream_lds_bytes(L.nt, nx, maxT, mode);
   if (!lds) return hipErrorInvalidValue;
+  if (mode == kStreamAdj && nx > 8 * kStreamWaves) return hipErrorInvalidValue;
   const int bufsz = (int)(lds / 32);  // units per buffer
   hipError_t err = hipSuccess;
-#define FK_HS(NT)                                                                              \
+#define FK_HS_MODE(NT, MODE)                                                                   \
   {                                                                                            \
-    auto k = had_stream_kernel<DTV, NT, kStreamW, kStreamWaves>;                               \
+    auto k = had_stream_kernel<DTV, NT, kStreamW, kStreamWaves, MODE>;                         \
     if ((err = set_lds(k, lds)) != hipSuccess) return err;                                     \
     hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kStreamWaves), lds, L.stream, recs, wg_ptr,    \
                        (const u32x4 *)bop, fstage, nx, bufsz, part, (const u32x4 *)L.zero_page); \
+  }
+#define FK_HS(NT)                         \
+  {                                       \
+    if (mode == kStreamAdj)               \
+      FK_HS_MODE(NT, kStreamAdj)          \
+    else                                  \
+      FK_HS_MODE(NT, kStreamFwd)          \
   }
 #define FK_HS_DT(DT)           \
   {                            \
@@ -1132,6 +1224,7 @@ hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const i
   }
   FK_DISPATCH_DT(FK_HS_DT);
 #undef FK_HS
+#undef FK_HS_MODE
 #undef FK_HS_DT
   return hipGetLastError();
 }

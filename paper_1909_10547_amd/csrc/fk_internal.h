@@ -79,7 +79,8 @@ struct StreamSeg {
   const uint4 *a1;    // block 1, nullptr when the item has one block
   int32_t nv0, nv1;   // rows of the two blocks (nv1 = 0: absent)
   int32_t KE, T;      // units per row, k-steps (ceil(KE / 4))
-  int32_t flav;       // row flavour a: the PDF row of the epilogue
+  int32_t flav;       // forward: row flavour a, the PDF row of the epilogue;
+                      // adjoint: first row of the pair in the padded weights
   int32_t last;       // 1 on the item's last group: write its partial sums
   int64_t bop_off;    // staged B operand of the group, in 16-byte units
   int32_t slot;       // first partial slot of the item
@@ -88,6 +89,10 @@ struct StreamSeg {
 constexpr int kAdjWaves = 8;      // waves per workgroup of the hadronic adjoint (x split 8 ways)
 constexpr int kStreamW = 8;       // k-steps in flight per wave in the stream kernel
 constexpr int kStreamWaves = 8;   // waves per workgroup of the stream kernel (2 per SIMD)
+constexpr int kStreamFwd = 0;     // stream kernel modes: forward (PDF-row epilogue) ...
+constexpr int kStreamAdj = 1;     // ... and adjoint (weighted row sums, gradient rows)
+constexpr int kAdjPairsPerItem = 4;  // block pairs per item of the stream adjoint
+constexpr int kAdjWRow = 36;  // floats per column of a pair's staged weights (32 rows + pad)
 
 // DIS stream kernel: one group of a table (forward groups in k order).
 struct DisGroupRef {
@@ -152,15 +157,23 @@ struct ConvLaunch {
 };
 constexpr int kZeroPageBytes = 4096;
 
+// Stages the B operands of ``ngd`` descriptors; with ``fstage`` also the
+// FP32 PDF rows [nflav][nx][RP]; with ``wstage`` also the adjoint weights
+// of ``nwpair`` block pairs, [pair][RP][kAdjWRow]: element (P, n, q) =
+// gout[wrow[32 P + q]][c0 + n] * s, zero where wrow < 0, q >= 32 or n >= ncols.
 hipError_t launch_stage_b(const ConvLaunch &L, const GroupDesc *d_gd, const int32_t *rowtab,
                           int ngd, const float *pdf,
                           const float *gout, const float *scale_all, uint4 *bop, int *counter,
-                          float *fstage = nullptr, int nflav = 0, int nx = 0);
+                          float *fstage = nullptr, int nflav = 0, int nx = 0,
+                          const int32_t *wrow = nullptr, float *wstage = nullptr, int nwpair = 0);
 // LDS of the stream kernel for (nt, nx, maxT); 0 when it does not fit.
-size_t had_stream_lds_bytes(int nt, int nx, int maxT);
+size_t had_stream_lds_bytes(int nt, int nx, int maxT, int mode = kStreamFwd);
+// Stream kernel.  Forward: fstage = FP32 PDF rows [F][nx][RP], part =
+// partial slots [slot][16][kRpMax].  Adjoint: fstage = the staged weights
+// [pair][RP][kAdjWRow], part = gradient slots [slot][nx][kRpMax]; nx <= 64.
 hipError_t launch_had_stream(const ConvLaunch &L, const StreamSeg *recs, const int32_t *wg_ptr,
                              int grid, const uint4 *bop, const float *fstage, int nx, int maxT,
-                             float *part);
+                             float *part, int mode = kStreamFwd);
 hipError_t launch_had_fwd(const ConvLaunch &L, const FwdItem *items, int nitems, const SegRef *segs,
                           const GroupDesc *gd, const uint4 *bop, const float *pdf, int nx,
                           int lds_units, float *part, int *counter, int grid);

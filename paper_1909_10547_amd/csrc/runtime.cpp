@@ -160,6 +160,31 @@ static void rebalance(std::vector<std::vector<int>> &lists, std::vector<double> 
     std::stable_sort(l.begin(), l.end(), [&](int x, int y) { return cost[x] > cost[y]; });
 }
 
+// Static work lists: items longest first to the least loaded of G lists,
+// then the local search above.
+static std::vector<std::vector<int>> partition_items(const std::vector<double> &cost, int G) {
+  std::vector<int> order(cost.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<std::vector<int>> lists(G);
+  std::vector<double> load(G, 0.0);
+  std::vector<std::pair<double, int>> heap;  // (load, list), min-heap
+  for (int g = 0; g < G; ++g) heap.push_back({0.0, g});
+  auto cmp = [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+    return x.first != y.first ? x.first > y.first : x.second > y.second;
+  };
+  std::make_heap(heap.begin(), heap.end(), cmp);
+  for (int k : order) {
+    std::pop_heap(heap.begin(), heap.end(), cmp);
+    lists[heap.back().second].push_back(k);
+    heap.back().first += cost[k];
+    load[heap.back().second] += cost[k];
+    std::push_heap(heap.begin(), heap.end(), cmp);
+  }
+  rebalance(lists, load, cost);
+  return lists;
+}
+
 static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) {
   const bool had = p.kind == FK_HAD;
   const int X = p.X, F = p.F;
@@ -503,6 +528,95 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     row_ptr.push_back((int32_t)entries.size());
   }
 
+  // ---- streaming hadronic adjoint.  Items: one adjoint group of a table
+  // over a run of kAdjPairsPerItem block pairs (a split that depends on the
+  // table alone); records: one block pair of an item.  Each wave keeps the
+  // gradient rows of its x indices in registers (at most 8 per wave, so
+  // X <= 64), and every record must last kStreamW k-steps per wave.  The
+  // weights gbar * s are staged per block pair (32 padded rows, zero past a
+  // table's last datapoint), column by column.
+  std::vector<StreamSeg> asrec;
+  std::vector<int32_t> awgptr, wrow, row_ptr2(1, 0);
+  std::vector<int64_t> entries2;
+  size_t apart2_floats = 0;
+  p.grid_astream = 0;
+  if (had && X >= kStreamWaves && X <= 8 * kStreamWaves) {
+    int minT = 1 << 30;
+    for (auto *t : ts)
+      for (auto &g : t->agroups) minT = std::min(minT, (g.KE + 3) / 4);
+    if (minT < (1 << 30) && minT * (X / kStreamWaves) >= kStreamW &&
+        had_stream_lds_bytes(7, X, p.maxT_adj, kStreamAdj)) {
+      std::vector<int> pbase(ts.size());
+      int nptot = 0;
+      for (size_t t = 0; t < ts.size(); ++t) {
+        pbase[t] = nptot;
+        nptot += ((ts[t]->N + 15) / 16 + 1) / 2;
+      }
+      wrow.assign((size_t)nptot * 32, -1);
+      for (size_t t = 0; t < ts.size(); ++t)
+        for (int r = 0; r < ts[t]->N; ++r) wrow[(size_t)pbase[t] * 32 + r] = p.row0[t] + r;
+      struct AItem {
+        int t, gi, pair0, pair1, slot;
+      };
+      std::vector<AItem> aitems;
+      std::vector<std::vector<int64_t>> rows2((size_t)F * X);
+      int slot = 0;
+      for (size_t t = 0; t < ts.size(); ++t) {
+        const int npair = ((ts[t]->N + 15) / 16 + 1) / 2;
+        for (size_t gi = 0; gi < ts[t]->agroups.size(); ++gi)
+          for (int p0 = 0; p0 < npair; p0 += kAdjPairsPerItem) {
+            aitems.push_back({(int)t, (int)gi, p0, std::min(npair, p0 + kAdjPairsPerItem), slot});
+            const int a = ts[t]->agroups[gi].a;
+            for (int al = 0; al < X; ++al)
+              rows2[(size_t)a * X + al].push_back((int64_t)slot * X * kRpMax + (int64_t)al * kRpMax);
+            ++slot;
+          }
+      }
+      apart2_floats = (size_t)slot * X * kRpMax;
+      for (auto &r : rows2) {
+        entries2.insert(entries2.end(), r.begin(), r.end());
+        row_ptr2.push_back((int32_t)entries2.size());
+      }
+      // cost in k-steps of the busiest wave, as for the forward lists
+      const int nal = (X + kStreamWaves - 1) / kStreamWaves;
+      std::vector<double> acost(aitems.size());
+      for (size_t k = 0; k < aitems.size(); ++k) {
+        const AItem &it = aitems[k];
+        const SegRef &sr = segs[asegidx[it.t][it.gi]];
+        acost[k] = 8.0 + (double)(it.pair1 - it.pair0) * ((double)((sr.KE + 3) / 4) * nal + 5.0);
+      }
+      const int G = std::min<int>(ncu, (int)aitems.size());
+      const auto lists = partition_items(acost, G);
+      awgptr.push_back(0);
+      for (int g = 0; g < G; ++g) {
+        for (int k : lists[g]) {
+          const AItem &it = aitems[k];
+          const Table *T = ts[it.t];
+          const int nblk = (T->N + 15) / 16;
+          const SegRef &sr = segs[asegidx[it.t][it.gi]];
+          for (int pp = it.pair0; pp < it.pair1; ++pp) {
+            const int bl0 = 2 * pp, bl1 = 2 * pp + 1;
+            StreamSeg r;
+            std::memset(&r, 0, sizeof r);
+            r.nv0 = std::min(16, T->N - 16 * bl0);
+            r.nv1 = bl1 < nblk ? std::min(16, T->N - 16 * bl1) : 0;
+            r.a0 = sr.base + (size_t)bl0 * X * sr.KE * 16;
+            r.a1 = r.nv1 ? sr.base + (size_t)bl1 * X * sr.KE * 16 : nullptr;
+            r.KE = sr.KE;
+            r.T = (sr.KE + 3) / 4;
+            r.flav = pbase[it.t] + pp;
+            r.last = pp == it.pair1 - 1;
+            r.bop_off = gd[sr.gdesc].bop_off;
+            r.slot = it.slot;
+            asrec.push_back(r);
+          }
+        }
+        awgptr.push_back((int32_t)asrec.size());
+      }
+      p.grid_astream = G;
+    }
+  }
+
   fk_status st;
   if ((st = upload(c, p, gd, &p.d_gd))) return st;
   if ((st = upload(c, p, rowtab, &p.d_rowtab))) return st;
@@ -519,6 +633,14 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     if ((st = upload(c, p, srec, &p.d_srec))) return st;
     if ((st = upload(c, p, wgptr, &p.d_wgptr))) return st;
   }
+  if (p.grid_astream) {
+    if ((st = upload(c, p, asrec, &p.d_asrec))) return st;
+    if ((st = upload(c, p, awgptr, &p.d_awgptr))) return st;
+    if ((st = upload(c, p, wrow, &p.d_wrow))) return st;
+    if ((st = upload(c, p, row_ptr2, &p.d_arow_ptr2))) return st;
+    if ((st = upload(c, p, entries2, &p.d_aentry2))) return st;
+    p.nwpair = (int)(wrow.size() / 32);
+  }
   if (p.dis_chunk) {
     if ((st = upload(c, p, dgroups, &p.d_dgroups))) return st;
     if ((st = upload(c, p, dwgs, &p.d_dwgs))) return st;
@@ -533,8 +655,12 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   p.d_bop = (uint4 *)d;
   if ((st = dev_alloc(c, (size_t)nslots * 16 * kRpMax * 4, &d, &p.allocs))) return st;
   p.d_fpart = (float *)d;
-  if ((st = dev_alloc(c, apart_floats * 4, &d, &p.allocs))) return st;
+  if ((st = dev_alloc(c, std::max(apart_floats, apart2_floats) * 4, &d, &p.allocs))) return st;
   p.d_apart = (float *)d;
+  if (p.grid_astream) {
+    if ((st = dev_alloc(c, (size_t)p.nwpair * kRpMax * kAdjWRow * 4, &d, &p.allocs))) return st;
+    p.d_wstage = (float *)d;
+  }
   if ((st = dev_alloc(c, kZeroPageBytes, &p.d_zero, &p.allocs))) return st;
   FK_TRY_HIP(c, hipMemset(p.d_zero, 0, kZeroPageBytes));
   if ((st = dev_alloc(c, 64, &d, &p.allocs))) return st;
@@ -636,11 +762,36 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
 
 hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int nrep, float *g,
                         int accumulate, hipStream_t s, Timing *tm) {
-  for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
-    const int ncols = std::min(kRpMax, nrep - c0);
+  // The stream adjoint (when the plan has it) runs in passes of 112 columns
+  // when 128 do not fit its LDS; FKCONV_NO_STREAM selects the per-item
+  // kernel, as for the forward.
+  const bool astream = p.kind == FK_HAD && p.grid_astream > 0 &&
+                       std::getenv("FKCONV_NO_STREAM") == nullptr;
+  const int chunk =
+      astream && !had_stream_lds_bytes(8, p.X, p.maxT_adj, kStreamAdj) ? 112 : kRpMax;
+  for (int c0 = 0; c0 < nrep; c0 += chunk) {
+    const int ncols = std::min(chunk, nrep - c0);
     ConvLaunch L{p.dtype, pick_nt(ncols), ncols, c0, nrep, s, p.d_zero};
     const int RP = 16 * L.nt;
     hipError_t e;
+    if (astream) {
+      e = timed(tm, FK_K_STAGE, s, [&] {
+        return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.d_rowtab, p.ngd_adj, pdf, gout, p.d_scale,
+                              p.d_bop, nullptr, nullptr, 0, 0, p.d_wrow, p.d_wstage, p.nwpair);
+      });
+      if (e != hipSuccess) return e;
+      e = timed(tm, FK_K_HAD_ADJ_STREAM, s, [&] {
+        return launch_had_stream(L, p.d_asrec, p.d_awgptr, p.grid_astream, p.d_bop, p.d_wstage,
+                                 p.X, p.maxT_adj, p.d_apart, kStreamAdj);
+      });
+      if (e != hipSuccess) return e;
+      e = timed(tm, FK_K_ADJ_REDUCE, s, [&] {
+        return launch_adj_reduce(L, p.F * p.X, p.d_arow_ptr2, p.d_aentry2, p.d_apart, accumulate,
+                                 g);
+      });
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (p.kind == FK_HAD) {
       e = timed(tm, FK_K_STAGE, s, [&] {
         return launch_stage_b(L, p.d_gd + p.ngd_fwd, p.d_rowtab, p.ngd_adj, pdf, nullptr, p.d_scale, p.d_bop,

@@ -69,6 +69,15 @@ struct Plan {
   int32_t *d_wgptr = nullptr;
   int grid_stream = 0;        // 0: the plan does not use the stream kernel
   float *d_fstage = nullptr;  // [F][X][RP] FP32 PDF rows of the epilogue
+  // streaming hadronic adjoint: its own records, items and CSR of slots
+  StreamSeg *d_asrec = nullptr;
+  int32_t *d_awgptr = nullptr;
+  int grid_astream = 0;       // 0: the plan uses the per-item adjoint kernel
+  int32_t *d_wrow = nullptr;  // [pair][32] padded weight row -> output row (-1: padding)
+  int nwpair = 0;
+  float *d_wstage = nullptr;  // [pair][RP][kAdjWRow] weights gbar * s
+  int32_t *d_arow_ptr2 = nullptr;
+  int64_t *d_aentry2 = nullptr;
   // streaming DIS forward
   DisGroupRef *d_dgroups = nullptr;
   DisStreamWG *d_dwgs = nullptr;

@@ -275,7 +275,7 @@ def fk_chi2(ctx, cov: int, sigma, data, chi2=None, dchi2_dsigma=None, want_grad=
 # kernel timing
 # ---------------------------------------------------------------------------
 KERNEL_KINDS = ["stage", "had_fwd", "dis_fwd", "fwd_reduce", "had_adj", "dis_adj",
-                "adj_reduce", "chi2", "had_stream", "dis_stream"]
+                "adj_reduce", "chi2", "had_stream", "dis_stream", "had_adj_stream"]
 
 
 def fk_timing_enable(ctx, enable: bool = True):

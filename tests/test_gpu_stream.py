@@ -158,3 +158,63 @@ def test_timing_kinds_name_the_kernel_that_ran():
                 assert kt["fwd_reduce"][1] == 2
         fkconv.fk_unload_table(c.ctx, h)
         fkconv.fk_unload_table(c.ctx, hd)
+
+
+def run_adj(c, h, x, gbar, stream):
+    if stream:
+        os.environ.pop("FKCONV_NO_STREAM", None)
+    else:
+        os.environ["FKCONV_NO_STREAM"] = "1"
+    try:
+        g = fkconv.fk_conv_backward(c.ctx, h, x, gbar)
+        torch.cuda.synchronize()
+    finally:
+        os.environ.pop("FKCONV_NO_STREAM", None)
+    return g
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f32", "e4m3"])
+@pytest.mark.parametrize("R", [1, 16, 100, 200])
+def test_adjoint_stream_against_item_kernel_and_oracle(fmt, R):
+    """Hadronic adjoint: the stream kernel (gradient rows in registers, one
+    record per block pair) against the per-item kernel and the oracle's
+    gradient of the stored operands, on a group of tables with partial last
+    blocks and odd block counts."""
+    w = synth.had_fit_workload(scale=0.12)
+    tabs = [w.table(d) for d in range(len(w.ndata))]
+    pdf = w.pdf(R).astype(np.float32).astype(np.float64)
+    N = sum(t.ndata for t in tabs)
+    gbar = np.random.default_rng(R).normal(size=(N, R)).astype(np.float32).astype(np.float64)
+    say(f"case fmt={fmt} R={R} ndata={[t.ndata for t in tabs]}")
+    with fkconv.Context(0) as c:
+        hs = [c.load(t, fmt) for t in tabs]
+        g = fkconv.fk_group_create(c.ctx, hs)
+        x = torch.from_numpy(pdf.astype(np.float32)).cuda()
+        gb = torch.from_numpy(gbar.astype(np.float32)).cuda()
+        fkconv.fk_timing_read(c.ctx)
+        fkconv.fk_timing_enable(c.ctx, True)
+        gs = run_adj(c, g, x, gb, True)
+        fkconv.fk_timing_enable(c.ctx, False)
+        kt = fkconv.fk_timing_read(c.ctx)
+        gp = run_adj(c, g, x, gb, False)
+        assert torch.equal(run_adj(c, g, x, gb, True), gs), "stream adjoint is not deterministic"
+        fkconv.fk_unload_table(c.ctx, g)
+        for h in hs:
+            fkconv.fk_unload_table(c.ctx, h)
+    used = "stream" if kt["had_adj_stream"][1] else "per-item"
+    say(f"  default path: {used} kernel")
+    if fmt != "e4m3":
+        assert kt["had_adj_stream"][1] > 0, "the stream adjoint should apply to these tables"
+    q = np.zeros_like(pdf)
+    absterms = np.zeros_like(pdf)
+    off = 0
+    for t in tabs:
+        q += oracle.had_grad_quantized(t.mask, t.fk, pdf, gbar[off:off + t.ndata], fmt)
+        absterms += oracle.had_grad(t.mask, np.abs(t.fk), np.abs(pdf), np.abs(gbar[off:off + t.ndata]))
+        off += t.ndata
+    tol = 1e-4 if fmt == "e4m3" else 1e-5
+    scale = np.where(absterms > 0, absterms, 1.0)
+    for name, y in (("stream", gs), ("per-item", gp)):
+        e = float(np.max(np.abs(y.double().cpu().numpy() - q) / scale))
+        say(f"  {name}: stored-operand error {e:.2e} of sum|terms|")
+        assert e <= tol, name
