@@ -130,6 +130,8 @@ def main() -> int:
                     help="FP32 table size of the large DIS set")
     ap.add_argument("--profile-bf16", action="store_true",
                     help="only load the BF16 tables and run the BF16 step (for profiler runs)")
+    ap.add_argument("--profile-adj", action="store_true",
+                    help="only load the BF16 tables and run the BF16 hadronic adjoint (for profiler runs)")
     ap.add_argument("--profile-dis", action="store_true",
                     help="only the DIS bandwidth set, BF16, R=1 (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -187,6 +189,15 @@ def main() -> int:
             fkconv.fk_conv_had(c.ctx, gb, x)
         torch.cuda.synchronize()
         print(json.dumps({"profile_bf16_steps": args.warmup + args.steps}))
+        return 0
+    if args.profile_adj:
+        x = torch.from_numpy(pdf64.astype(np.float32)).cuda()
+        Nt = sum(t.ndata for t in tabs)
+        gbar = torch.ones((Nt, R), dtype=torch.float32, device="cuda")
+        for _ in range(args.warmup + args.steps):
+            fkconv.fk_conv_backward(c.ctx, gb, x, gbar)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_adj_steps": args.warmup + args.steps}))
         return 0
     hf = [c.load(t, "f32") for t in tabs]
     gf = fkconv.fk_group_create(c.ctx, hf)

@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(64 * S, 1)
   };
 
   // refill cursor: record rr, job alpha r_al, k-step r_t
-  int rr = r_begin, r_al = w, r_t = 0, rpar = 0;
+  int rr = r_begin, r_al = w, r_t = 0;
   bool r_done = false;
   StreamSeg Rq = recs[rr];
   // forward copy: the two tiles of a pair alternate at every alpha (see the
@@ -567,10 +567,6 @@ __global__ void __launch_bounds__(64 * S, 1)
             r_done = true;
           } else {
             Rq = recs[rr];
-            rpar ^= 1;
-            __builtin_amdgcn_sched_barrier(0);
-            stage(Rq, rpar);
-            __builtin_amdgcn_sched_barrier(0);
           }
         }
         pa0 = as_global(Rq.a0) + r_al * stride0(Rq);
@@ -722,12 +718,20 @@ __global__ void __launch_bounds__(64 * S, 1)
           wait_vmcnt<2 * W - 2>();
           lds_barrier();
           read_b();
+          // the buffer of the record just finished is free: copy the record
+          // after the new one into it, a whole record ahead of its use
+          if (cr + 1 < r_end) {
+            __builtin_amdgcn_sched_barrier(0);
+            stage(recs[cr + 1], cpar ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
     }
   };
 
   stage(Rq, 0);
+  if (r_begin + 1 < r_end) stage(recs[r_begin + 1], 1);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int i = 0; i < W; ++i) refill(a0[i], a1[i]);
@@ -1083,17 +1087,43 @@ __global__ void __launch_bounds__(kThreads)
   *(vec *)(out + (size_t)orow * R + c0 + col) = sc * acc;
 }
 
-__global__ void __launch_bounds__(kThreads)
+// One output row (flavour, x) per workgroup: kAdjRedRuns groups of 128
+// threads (one per column) each add a contiguous run of the row's slots in
+// list order, issuing the loads eight at a time; the runs' sums are then
+// added in run order.  A fixed order either way.
+constexpr int kAdjRedRuns = 4;
+__global__ void __launch_bounds__(128 * kAdjRedRuns)
     adj_reduce_kernel(const int32_t *__restrict__ row_ptr, const int64_t *__restrict__ entry,
                       const float *__restrict__ apart, int R, int c0, int ncols, int accumulate,
                       float *__restrict__ g) {
+  static_assert(kRpMax <= 128, "one thread per column");
+  __shared__ float run_sum[kAdjRedRuns][128];
   const int o = blockIdx.x;
   const int k0 = row_ptr[o], k1 = row_ptr[o + 1];
-  for (int col = threadIdx.x; col < ncols; col += kThreads) {
-    float acc = 0.f;
-    for (int k = k0; k < k1; ++k) acc += apart[entry[k] + col];
+  const int col = threadIdx.x & 127;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
+  const int n = k1 - k0, per = (n + kAdjRedRuns - 1) / kAdjRedRuns;
+  const int ka = k0 + min(n, q * per), kb = k0 + min(n, (q + 1) * per);
+  float acc = 0.f;
+  if (col < ncols) {
+    int k = ka;
+    for (; k + 8 <= kb; k += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = apart[entry[k + u] + col];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; k < kb; ++k) acc += apart[entry[k] + col];
+  }
+  run_sum[q][col] = acc;
+  __syncthreads();
+  if (q == 0 && col < ncols) {
+    float sum = run_sum[0][col];
+#pragma unroll
+    for (int r = 1; r < kAdjRedRuns; ++r) sum += run_sum[r][col];
     float *p = g + (size_t)o * R + c0 + col;
-    *p = accumulate ? *p + acc : acc;
+    *p = accumulate ? *p + sum : sum;
   }
 }
 
@@ -1354,8 +1384,9 @@ hipError_t launch_adj_reduce(const ConvLaunch &L, int nrows_out, const int32_t *
                              const int64_t *entry_off, const float *apart, int accumulate,
                              float *g) {
   if (nrows_out <= 0) return hipSuccess;
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nrows_out), dim3(kThreads), 0, L.stream, row_ptr,
-                     entry_off, apart, L.R, L.c0, L.ncols, accumulate, g);
+  if (L.ncols > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nrows_out), dim3(128 * kAdjRedRuns), 0, L.stream,
+                     row_ptr, entry_off, apart, L.R, L.c0, L.ncols, accumulate, g);
   return hipGetLastError();
 }
 
