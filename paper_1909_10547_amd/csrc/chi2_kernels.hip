@@ -6,7 +6,9 @@
 // workgroup per block) and the triangular inverse M_b = L_b^{-1} (one wave
 // per 64 columns).  Per call: y = M e (e = sigma - D, lower-triangular
 // product), chi2_r = sum y^2, and the gradient 2 C^{-1} e = 2 M^T y
-// (upper-triangular product).  Everything is binary64; partial sums are
+// (upper-triangular product).  Both products are split along k into
+// entries of a few 32 x 32 tiles, so that every block's rows are worked on
+// by many workgroups at once.  Everything is binary64; partial sums are
 // reduced in a fixed order.
 #include "fk_internal.h"
 
@@ -90,111 +92,142 @@ __global__ void clear_upper_kernel(const int32_t *__restrict__ nb, const int64_t
   }
 }
 
-// y = M e for one 32-row tile of a block and 32 columns; also the tile's
-// column sums of y^2.
+// chi2 of one replica column per workgroup: thread t adds the row tiles
+// t, t + 256, ... in order, then a fixed-shape tree over the threads.
 __global__ void __launch_bounds__(256)
-    trmm_lower_kernel(const int32_t *__restrict__ rt_block, const int32_t *__restrict__ rt_row,
-                      const int32_t *__restrict__ nb, const int64_t *__restrict__ off,
-                      const int32_t *__restrict__ roff, const double *__restrict__ M,
-                      const float *__restrict__ sigma, const double *__restrict__ data, int R,
-                      int c0, int ncols, double *__restrict__ y, double *__restrict__ part) {
+    chi2_reduce_kernel(int nrt, const double *__restrict__ part, int c0, double *__restrict__ chi2) {
+  __shared__ double sh[256];
+  const int col = blockIdx.x;
+  double t = 0.0;
+  for (int rt = threadIdx.x; rt < nrt; rt += 256) t += part[(size_t)rt * kRpMax + col];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) chi2[c0 + col] = sh[0];
+}
+
+// Split products.  A work entry {rt, t0, t1, slot} (slot = the entry's
+// index in its list) asks for the partial
+// product of row tile rt (32 rows of its block) over the k tiles [t0, t1):
+//   lower: P = M[rows, k] e[k, cols]        (k tiles up to the diagonal)
+//   upper: P = M[i, rows]^T y[i, cols]      (i tiles from the diagonal on)
+// written to slot [32][kRpMax].  The entries of one row tile are added in
+// list order by split_reduce_kernel, so the result is a fixed-order sum.
+// Each workgroup computes 32 rows x 32 columns with 256 threads (4 rows per
+// thread); the tiles of the next k step are read into registers while the
+// current ones are multiplied.
+template <bool UPPER>
+__global__ void __launch_bounds__(256)
+    trmm_split_kernel(const int4 *__restrict__ work, const int32_t *__restrict__ rt_block,
+                      const int32_t *__restrict__ rt_row, const int32_t *__restrict__ nb,
+                      const int64_t *__restrict__ off, const int32_t *__restrict__ roff,
+                      const double *__restrict__ M, const float *__restrict__ sigma,
+                      const double *__restrict__ data, const double *__restrict__ y, int R,
+                      int c0, int ncols, double *__restrict__ spart) {
   __shared__ double sm[kCT][kCT + 1];
-  __shared__ double se[kCT][kCT + 1];
-  __shared__ double sq[8][kCT];
-  const int rt = blockIdx.x;
+  __shared__ double so[kCT][kCT + 1];
+  const int4 wk = work[blockIdx.x];
+  const int rt = wk.x, t0 = wk.y, t1 = wk.z, slot = wk.w;
   const int b = rt_block[rt], r0 = rt_row[rt];
   const int n = nb[b];
   const double *m = M + off[b];
   const int base = roff[b];
-  const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;  // column, row group of 4
+  const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;
   const int col = blockIdx.y * kCT + tc;
+  // this thread's four elements of each 32 x 32 tile: (i, cc) with
+  // i = threadIdx.x / 32 + 8 q
+  double vm[4], vo[4];
+  auto fetch = [&](int t) {
+    const int k0 = t * kCT;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = tr + 8 * q, cc = tc;
+      // M tile: lower reads M[r0 + rr][k0 + cc]; upper reads M[k0 + rr][r0 + cc]
+      const int gi = UPPER ? k0 + rr : r0 + rr, gk = UPPER ? r0 + cc : k0 + cc;
+      vm[q] = (gi < n && gk < n) ? m[(size_t)gi * n + gk] : 0.0;
+      // operand tile row k0 + rr, column blockIdx.y * 32 + cc
+      const int ok = k0 + rr, oc = blockIdx.y * kCT + cc;
+      double v = 0.0;
+      if (ok < n && oc < ncols) {
+        if (UPPER)
+          v = y[(size_t)(base + ok) * kRpMax + oc];
+        else
+          v = (double)sigma[(size_t)(base + ok) * R + c0 + oc] - data[base + ok];
+      }
+      vo[q] = v;
+    }
+  };
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int kend = min(n, r0 + kCT);
-  for (int k0 = 0; k0 < kend; k0 += kCT) {
-    for (int i = threadIdx.x; i < kCT * kCT; i += 256) {
-      const int rr = i / kCT, cc = i % kCT;
-      const int gr = r0 + rr, gk = k0 + cc;
-      sm[rr][cc] = (gr < n && gk < n) ? m[(size_t)gr * n + gk] : 0.0;
-      const int ek = k0 + rr, ec = blockIdx.y * kCT + cc;
-      double e = 0.0;
-      if (ek < n && ec < ncols)
-        e = (double)sigma[(size_t)(base + ek) * R + c0 + ec] - data[base + ek];
-      se[rr][cc] = e;
+  fetch(t0);
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sm[tr + 8 * q][tc] = vm[q];
+      so[tr + 8 * q][tc] = vo[q];
     }
     __syncthreads();
+    if (t + 1 < t1) fetch(t + 1);
 #pragma unroll 4
     for (int kk = 0; kk < kCT; ++kk) {
-      const double ev = se[kk][tc];
+      const double ov = so[kk][tc];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += sm[4 * tr + q][kk] * ev;
+      for (int q = 0; q < 4; ++q)
+        acc[q] += (UPPER ? sm[kk][4 * tr + q] : sm[4 * tr + q][kk]) * ov;
     }
-    __syncthreads();
+  }
+  double *dst = spart + (size_t)slot * kCT * kRpMax;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[(size_t)(4 * tr + q) * kRpMax + col] = acc[q];
+}
+
+// Sum of the entries of each row tile in list order.  Lower: y and the
+// tile's column sums of y^2; upper: 2 M^T y into the float gradient.
+template <bool UPPER>
+__global__ void __launch_bounds__(256)
+    split_reduce_kernel(const int32_t *__restrict__ wptr,
+                        const int32_t *__restrict__ rt_block, const int32_t *__restrict__ rt_row,
+                        const int32_t *__restrict__ nb, const int32_t *__restrict__ roff,
+                        const double *__restrict__ spart, int R, int c0, int ncols,
+                        double *__restrict__ y, double *__restrict__ part,
+                        float *__restrict__ dchi2) {
+  __shared__ double sq[8][kCT];
+  const int rt = blockIdx.x;
+  const int b = rt_block[rt], r0 = rt_row[rt];
+  const int n = nb[b];
+  const int base = roff[b];
+  const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;
+  const int col = blockIdx.y * kCT + tc;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // an entry's slot is its index in the list
+  for (int e = wptr[rt]; e < wptr[rt + 1]; ++e) {
+    const double *src = spart + (size_t)e * kCT * kRpMax;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += src[(size_t)(4 * tr + q) * kRpMax + col];
   }
   double ss = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int gr = r0 + 4 * tr + q;
     if (gr < n && col < ncols) {
-      y[(size_t)(base + gr) * kRpMax + col] = acc[q];
-      ss += acc[q] * acc[q];
+      if (UPPER) {
+        dchi2[(size_t)(base + gr) * R + c0 + col] = (float)(2.0 * acc[q]);
+      } else {
+        y[(size_t)(base + gr) * kRpMax + col] = acc[q];
+        ss += acc[q] * acc[q];
+      }
     }
   }
+  if (UPPER) return;
   sq[tr][tc] = ss;
   __syncthreads();
   if (tr == 0) {
     double t = 0.0;
     for (int g = 0; g < 8; ++g) t += sq[g][tc];
     part[(size_t)rt * kRpMax + col] = t;
-  }
-}
-
-__global__ void chi2_reduce_kernel(int nrt, const double *__restrict__ part, int c0, int ncols,
-                                   double *__restrict__ chi2) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncols) return;
-  double t = 0.0;
-  for (int rt = 0; rt < nrt; ++rt) t += part[(size_t)rt * kRpMax + col];
-  chi2[c0 + col] = t;
-}
-
-// w = M^T y for one 32-row tile (rows k of w) and 32 columns; writes 2w.
-__global__ void __launch_bounds__(256)
-    trmm_upper_kernel(const int32_t *__restrict__ rt_block, const int32_t *__restrict__ rt_row,
-                      const int32_t *__restrict__ nb, const int64_t *__restrict__ off,
-                      const int32_t *__restrict__ roff, const double *__restrict__ M,
-                      const double *__restrict__ y, int R, int c0, int ncols,
-                      float *__restrict__ dchi2) {
-  __shared__ double sm[kCT][kCT + 1];  // sm[i][k] = M[i0+i][k0+k]
-  __shared__ double sy[kCT][kCT + 1];
-  const int rt = blockIdx.x;
-  const int b = rt_block[rt], k0 = rt_row[rt];
-  const int n = nb[b];
-  const double *m = M + off[b];
-  const int base = roff[b];
-  const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;
-  const int col = blockIdx.y * kCT + tc;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i0 = k0; i0 < n; i0 += kCT) {
-    for (int i = threadIdx.x; i < kCT * kCT; i += 256) {
-      const int rr = i / kCT, cc = i % kCT;
-      const int gi = i0 + rr, gk = k0 + cc;
-      sm[rr][cc] = (gi < n && gk < n) ? m[(size_t)gi * n + gk] : 0.0;
-      const int yc = blockIdx.y * kCT + cc;
-      sy[rr][cc] = (gi < n && yc < ncols) ? y[(size_t)(base + gi) * kRpMax + yc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int ii = 0; ii < kCT; ++ii) {
-      const double yv = sy[ii][tc];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += sm[ii][4 * tr + q] * yv;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gk = k0 + 4 * tr + q;
-    if (gk < n && col < ncols) dchi2[(size_t)(base + gk) * R + c0 + col] = (float)(2.0 * acc[q]);
   }
 }
 
@@ -208,21 +241,28 @@ hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off
   return hipGetLastError();
 }
 
-hipError_t launch_chi2(int nblocks, int nrt, const int32_t *d_rt_block, const int32_t *d_rt_row,
-                       const int32_t *d_n, const int64_t *d_off, const int32_t *d_roff,
-                       const double *d_linv, const float *sigma, const double *data, int R,
-                       int c0, int ncols, double *d_y, double *d_part, double *chi2,
-                       float *dchi2, hipStream_t s) {
-  (void)nblocks;
-  if (nrt <= 0) return hipSuccess;
-  const dim3 grid(nrt, (ncols + kCT - 1) / kCT);
-  hipLaunchKernelGGL(trmm_lower_kernel, grid, dim3(256), 0, s, d_rt_block, d_rt_row, d_n, d_off,
-                     d_roff, d_linv, sigma, data, R, c0, ncols, d_y, d_part);
-  hipLaunchKernelGGL(chi2_reduce_kernel, dim3((ncols + 127) / 128), dim3(128), 0, s, nrt, d_part,
-                     c0, ncols, chi2);
-  if (dchi2)
-    hipLaunchKernelGGL(trmm_upper_kernel, grid, dim3(256), 0, s, d_rt_block, d_rt_row, d_n, d_off,
-                       d_roff, d_linv, (const double *)d_y, R, c0, ncols, dchi2);
+hipError_t launch_chi2(const Chi2Plan &P, const double *d_linv, const float *sigma,
+                       const double *data, int R, int c0, int ncols, double *chi2, float *dchi2,
+                       hipStream_t s) {
+  if (P.nrt <= 0) return hipSuccess;
+  const int nct = (ncols + kCT - 1) / kCT;
+  hipLaunchKernelGGL(trmm_split_kernel<false>, dim3(P.nlw, nct), dim3(256), 0, s, P.d_lw,
+                     P.d_rt_block, P.d_rt_row, P.d_n, P.d_off, P.d_roff, d_linv, sigma, data,
+                     (const double *)nullptr, R, c0, ncols, P.d_spart);
+  hipLaunchKernelGGL(split_reduce_kernel<false>, dim3(P.nrt, nct), dim3(256), 0, s, P.d_lptr,
+                     P.d_rt_block, P.d_rt_row, P.d_n, P.d_roff,
+                     (const double *)P.d_spart, R, c0, ncols, P.d_y, P.d_part, (float *)nullptr);
+  hipLaunchKernelGGL(chi2_reduce_kernel, dim3(ncols), dim3(256), 0, s, P.nrt, P.d_part, c0, chi2);
+  if (dchi2) {
+    hipLaunchKernelGGL(trmm_split_kernel<true>, dim3(P.nuw, nct), dim3(256), 0, s, P.d_uw,
+                       P.d_rt_block, P.d_rt_row, P.d_n, P.d_off, P.d_roff, d_linv,
+                       (const float *)nullptr, (const double *)nullptr, (const double *)P.d_y, R,
+                       c0, ncols, P.d_spart);
+    hipLaunchKernelGGL(split_reduce_kernel<true>, dim3(P.nrt, nct), dim3(256), 0, s, P.d_uptr,
+                       P.d_rt_block, P.d_rt_row, P.d_n, P.d_roff,
+                       (const double *)P.d_spart, R, c0, ncols, (double *)nullptr,
+                       (double *)nullptr, dchi2);
+  }
   return hipGetLastError();
 }
 

@@ -201,10 +201,22 @@ hipError_t launch_adj_reduce(const ConvLaunch &L, int nrows_out, const int32_t *
 // chi2 (chi2_kernels.hip)
 hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off, double *d_a,
                            double *d_linv, int32_t *d_flag, int maxn, hipStream_t s);
-hipError_t launch_chi2(int nblocks, int nrt, const int32_t *d_rt_block, const int32_t *d_rt_row,
-                       const int32_t *d_n, const int64_t *d_off, const int32_t *d_roff,
-                       const double *d_linv, const float *sigma, const double *data, int R,
-                       int c0, int ncols, double *d_y, double *d_part, double *chi2,
-                       float *dchi2, hipStream_t s);
+// Per-call chi2 work of a covariance: row tiles (32 rows of a block), and
+// the split products: entries {row tile, first k tile, end k tile, slot},
+// those of row tile rt at [ptr[rt], ptr[rt + 1]).
+constexpr int kChi2Split = 4;  // k tiles per entry of the split products
+struct Chi2Plan {
+  int nrt = 0, nlw = 0, nuw = 0;
+  const int32_t *d_rt_block = nullptr, *d_rt_row = nullptr, *d_n = nullptr, *d_roff = nullptr;
+  const int64_t *d_off = nullptr;
+  const int4 *d_lw = nullptr, *d_uw = nullptr;
+  const int32_t *d_lptr = nullptr, *d_uptr = nullptr;
+  double *d_spart = nullptr;  // [max(nlw, nuw)][32][kRpMax]
+  double *d_y = nullptr;      // [ntot][kRpMax]
+  double *d_part = nullptr;   // [nrt][kRpMax]
+};
+hipError_t launch_chi2(const Chi2Plan &P, const double *d_linv, const float *sigma,
+                       const double *data, int R, int c0, int ncols, double *chi2, float *dchi2,
+                       hipStream_t s);
 
 }  // namespace fk

@@ -1130,6 +1130,24 @@ fk_status fk_load_covariance(fk_ctx *ctx, int32_t nblocks, const int32_t *block_
   }
   cv->ntot = r;
   cv->nrt = (int)rtb.size();
+  // split products: lower entries of row tile r cover k tiles [0, r], upper
+  // entries the i tiles [r, nt), kChi2Split tiles per entry
+  std::vector<int4> lw, uw;
+  std::vector<int32_t> lptr(1, 0), uptr(1, 0);
+  {
+    int rt = 0;
+    for (int b = 0; b < nblocks; ++b) {
+      const int nt = (block_n[b] + 31) / 32;
+      for (int rr = 0; rr < nt; ++rr, ++rt) {
+        for (int t0 = 0; t0 <= rr; t0 += kChi2Split)
+          lw.push_back(make_int4(rt, t0, std::min(rr + 1, t0 + kChi2Split), (int)lw.size()));
+        lptr.push_back((int32_t)lw.size());
+        for (int t0 = rr; t0 < nt; t0 += kChi2Split)
+          uw.push_back(make_int4(rt, t0, std::min(nt, t0 + kChi2Split), (int)uw.size()));
+        uptr.push_back((int32_t)uw.size());
+      }
+    }
+  }
   FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
   std::vector<std::pair<void *, size_t>> tmp;
   void *d = nullptr;
@@ -1159,12 +1177,44 @@ fk_status fk_load_covariance(fk_ctx *ctx, int32_t nblocks, const int32_t *block_
   cv->d_y = (double *)d;
   if ((st = dev_alloc(ctx, (size_t)cv->nrt * kRpMax * 8, &d, &cv->allocs))) return fail(st);
   cv->d_part = (double *)d;
+  Chi2Plan &P = cv->plan;
+  P.nrt = cv->nrt;
+  P.nlw = (int)lw.size();
+  P.nuw = (int)uw.size();
+  if ((st = dev_alloc(ctx, (size_t)std::max(P.nlw, P.nuw) * 32 * kRpMax * 8, &d, &cv->allocs)))
+    return fail(st);
+  P.d_spart = (double *)d;
+  int4 *d_lw = nullptr, *d_uw = nullptr;
+  int32_t *d_lptr = nullptr, *d_uptr = nullptr;
+  if ((st = dev_alloc(ctx, lw.size() * sizeof(int4), &d, &cv->allocs))) return fail(st);
+  d_lw = (int4 *)d;
+  if ((st = dev_alloc(ctx, uw.size() * sizeof(int4), &d, &cv->allocs))) return fail(st);
+  d_uw = (int4 *)d;
+  if ((st = dev_alloc(ctx, lptr.size() * 4, &d, &cv->allocs))) return fail(st);
+  d_lptr = (int32_t *)d;
+  if ((st = dev_alloc(ctx, uptr.size() * 4, &d, &cv->allocs))) return fail(st);
+  d_uptr = (int32_t *)d;
+  P.d_lw = d_lw;
+  P.d_uw = d_uw;
+  P.d_lptr = d_lptr;
+  P.d_uptr = d_uptr;
+  P.d_y = cv->d_y;
+  P.d_part = cv->d_part;
+  P.d_rt_block = cv->d_rt_block;
+  P.d_rt_row = cv->d_rt_row;
+  P.d_n = cv->d_n;
+  P.d_roff = cv->d_roff;
+  P.d_off = cv->d_off;
   hipError_t e = hipMemcpy(d_a, cov, (size_t)o * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(cv->d_n, cv->n.data(), nblocks * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(cv->d_off, off.data(), nblocks * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(cv->d_roff, roff.data(), nblocks * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(cv->d_rt_block, rtb.data(), rtb.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(cv->d_rt_row, rtr.data(), rtr.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_lw, lw.data(), lw.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_uw, uw.data(), uw.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_lptr, lptr.data(), lptr.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_uptr, uptr.data(), uptr.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(cv->d_linv, 0, (size_t)o * 8);
   if (e == hipSuccess) e = hipMemset(d_flag, 0, nblocks * 4);
   if (e == hipSuccess)
@@ -1219,9 +1269,8 @@ fk_status fk_chi2(fk_ctx *ctx, fk_cov cov, const float *sigma, const double *dat
   for (int c0 = 0; c0 < nrep; c0 += kRpMax) {
     const int ncols = std::min(kRpMax, nrep - c0);
     hipEvent_t ta = ctx->timing.begin((hipStream_t)stream);
-    hipError_t e = launch_chi2(cv->nblocks, cv->nrt, cv->d_rt_block, cv->d_rt_row, cv->d_n,
-                               cv->d_off, cv->d_roff, cv->d_linv, sigma, data, nrep, c0, ncols,
-                               cv->d_y, cv->d_part, chi2, dchi2_dsigma, (hipStream_t)stream);
+    hipError_t e = launch_chi2(cv->plan, cv->d_linv, sigma, data, nrep, c0, ncols, chi2,
+                               dchi2_dsigma, (hipStream_t)stream);
     ctx->timing.end(FK_K_CHI2, ta, (hipStream_t)stream);
     if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_chi2: launch failed: %s", hipGetErrorString(e));
   }

@@ -114,6 +114,7 @@ struct Cov {
   int32_t *d_n = nullptr, *d_roff = nullptr, *d_rt_block = nullptr, *d_rt_row = nullptr;
   int64_t *d_off = nullptr;
   double *d_y = nullptr, *d_part = nullptr;
+  Chi2Plan plan;  // device pointers of the per-call work
   std::vector<std::pair<void *, size_t>> allocs;
   uint64_t bytes = 0;
 };
