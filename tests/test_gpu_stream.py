@@ -218,3 +218,44 @@ def test_adjoint_stream_against_item_kernel_and_oracle(fmt, R):
         e = float(np.max(np.abs(y.double().cpu().numpy() - q) / scale))
         say(f"  {name}: stored-operand error {e:.2e} of sum|terms|")
         assert e <= tol, name
+
+
+@pytest.mark.parametrize("X,expect_adj_stream", [(8, None), (20, None), (64, True), (72, False)])
+def test_stream_kernels_across_grid_sizes(X, expect_adj_stream):
+    """Forward and adjoint at x-grids of 8 (each wave one x index), 20, 64
+    (the most gradient rows a wave keeps in registers) and 72 (the adjoint
+    falls back to the per-item kernel): stored-operand oracle, and, where
+    the grid decides it, the path that ran (read from the kernel timing
+    kinds; at 8 and 20 it depends on the group sizes)."""
+    rng = np.random.default_rng(X)
+    xg = synth.xgrid_geom(1e-6, 0.95, X)
+    N, R = 53, 16
+    # many ordered pairs, so that every group lasts the ring's eight k-steps
+    t = synth.draw_general_had_table(rng, xg, N, npairs=120)
+    f = synth.sample_pdf(synth.draw_pdf_params(rng), xg, R, 0.05, rng).astype(np.float32).astype(np.float64)
+    gbar = rng.normal(size=(N, R)).astype(np.float32).astype(np.float64)
+    say(f"case X={X} N={N} R={R} pairs={int(t.mask.sum())}")
+    with fkconv.Context(0) as c:
+        h = c.load(t, "bf16")
+        x = torch.from_numpy(f.astype(np.float32)).cuda()
+        gb = torch.from_numpy(gbar.astype(np.float32)).cuda()
+        fkconv.fk_timing_read(c.ctx)
+        fkconv.fk_timing_enable(c.ctx, True)
+        y = fkconv.fk_conv_had(c.ctx, h, x)
+        g = fkconv.fk_conv_backward(c.ctx, h, x, gb)
+        torch.cuda.synchronize()
+        fkconv.fk_timing_enable(c.ctx, False)
+        kt = fkconv.fk_timing_read(c.ctx)
+        fkconv.fk_unload_table(c.ctx, h)
+    say(f"  kernels: {({k: v[1] for k, v in kt.items() if v[1]})}")
+    assert (kt["had_adj_stream"][1] > 0) != (kt["had_adj"][1] > 0)
+    if expect_adj_stream is not None:
+        assert (kt["had_adj_stream"][1] > 0) == expect_adj_stream
+    qy = oracle.had_quantized(t.mask, t.fk, f, "bf16")
+    ay = oracle.had(t.mask, np.abs(t.fk), np.abs(f))
+    ey = float(np.max(np.abs(y.double().cpu().numpy() - qy) / np.where(ay > 0, ay, 1.0)))
+    qg = oracle.had_grad_quantized(t.mask, t.fk, f, gbar, "bf16")
+    ag = oracle.had_grad(t.mask, np.abs(t.fk), np.abs(f), np.abs(gbar))
+    eg = float(np.max(np.abs(g.double().cpu().numpy() - qg) / np.where(ag > 0, ag, 1.0)))
+    say(f"  forward {ey:.2e}, adjoint {eg:.2e} of sum|terms|")
+    assert ey <= 1e-5 and eg <= 1e-5
