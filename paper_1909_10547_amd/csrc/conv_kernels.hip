@@ -440,23 +440,28 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ---------------------------------------------------------------------------
-// Streaming hadronic forward.  Each workgroup walks a static list of
-// segment records (one group of one item each); the waves split alpha as in
-// had_fwd_kernel.  Seen from one wave, the FK tiles of its (group, alpha)
-// jobs form one flat stream of k-steps (T per job), and a ring of W k-steps
-// of both tiles of the pair stays in flight in registers, so the bytes in
-// flight do not depend on the group size.  Every k-step issues exactly two
-// loads, which keeps the compiler's waits on the ring exact.
+// Stream kernel (hadronic forward and adjoint).  Each workgroup walks a
+// static list of records: forward, one group of an item (a block pair and a
+// run of groups); adjoint, one block pair of an item (an adjoint group and a
+// run of block pairs).  The waves split alpha (alpha = w mod S).  Seen from
+// one wave, the FK tiles of its (record, alpha) jobs form one flat stream of
+// k-steps (T per job), and a ring of W k-steps of both tiles of the pair
+// stays in flight in registers, so the bytes in flight do not depend on the
+// group size.  Every k-step issues exactly two loads, which keeps the
+// compiler's waits on the ring exact.
 //
-// The B operand and the FP32 PDF row of the epilogue of each group go to one
-// of two LDS buffers by LDS-DMA, issued when the refill cursor enters the
-// group, W-1 k-steps before the first MFMA needs them; at every group change
-// each wave waits for its own copies (they were issued before the last
-// 2W-2 ring loads) and a workgroup barrier publishes them.  The buffer a
-// copy overwrites was released at the previous group change, provided every
-// group lasts at least W k-steps per wave (the host checks this).  At the
-// end of an item the four waves' partial sums are combined in a fixed order
-// in the buffer of the group just finished and written to the item's slots.
+// The B operand and the epilogue rows of each record (forward: the FP32 PDF
+// rows of its flavour; adjoint: the weights of its 32 datapoints) go to one
+// of two LDS buffers by LDS-DMA.  The copies of record r+1 are issued right
+// after the barrier that starts record r, which released the buffer of
+// record r-1; at the change to r+1 each wave waits for its own copies (they
+// were issued before all the ring loads of record r, at least 2W of them,
+// since every record lasts at least W k-steps per wave: the host checks
+// this) and a workgroup barrier publishes them.  Forward: at the end of an
+// item the waves' partial sums are combined in a fixed order in the buffer
+// of the record just finished and written to the item's slots.  Adjoint:
+// each wave keeps the gradient rows of its alpha in registers and writes
+// them to the item's slot at its end.
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
