@@ -204,7 +204,7 @@ hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off
 // Per-call chi2 work of a covariance: row tiles (32 rows of a block), and
 // the split products: entries {row tile, first k tile, end k tile, slot},
 // those of row tile rt at [ptr[rt], ptr[rt + 1]).
-constexpr int kChi2Split = 4;  // k tiles per entry of the split products
+constexpr int kChi2Split = 4;  // k tiles per entry of the split products (at least)
 struct Chi2Plan {
   int nrt = 0, nlw = 0, nuw = 0;
   const int32_t *d_rt_block = nullptr, *d_rt_row = nullptr, *d_n = nullptr, *d_roff = nullptr;

@@ -1131,19 +1131,22 @@ fk_status fk_load_covariance(fk_ctx *ctx, int32_t nblocks, const int32_t *block_
   cv->ntot = r;
   cv->nrt = (int)rtb.size();
   // split products: lower entries of row tile r cover k tiles [0, r], upper
-  // entries the i tiles [r, nt), kChi2Split tiles per entry
+  // entries the i tiles [r, nt); kChi2Split tiles per entry, more in large
+  // blocks so that a row tile has at most eight entries (the partial
+  // products then take at most 8 x 32 KiB per row tile)
   std::vector<int4> lw, uw;
   std::vector<int32_t> lptr(1, 0), uptr(1, 0);
   {
     int rt = 0;
     for (int b = 0; b < nblocks; ++b) {
       const int nt = (block_n[b] + 31) / 32;
+      const int kc = std::max(kChi2Split, (nt + 7) / 8);
       for (int rr = 0; rr < nt; ++rr, ++rt) {
-        for (int t0 = 0; t0 <= rr; t0 += kChi2Split)
-          lw.push_back(make_int4(rt, t0, std::min(rr + 1, t0 + kChi2Split), (int)lw.size()));
+        for (int t0 = 0; t0 <= rr; t0 += kc)
+          lw.push_back(make_int4(rt, t0, std::min(rr + 1, t0 + kc), (int)lw.size()));
         lptr.push_back((int32_t)lw.size());
-        for (int t0 = rr; t0 < nt; t0 += kChi2Split)
-          uw.push_back(make_int4(rt, t0, std::min(nt, t0 + kChi2Split), (int)uw.size()));
+        for (int t0 = rr; t0 < nt; t0 += kc)
+          uw.push_back(make_int4(rt, t0, std::min(nt, t0 + kc), (int)uw.size()));
         uptr.push_back((int32_t)uw.size());
       }
     }

@@ -54,6 +54,31 @@ def test_chi2_matches_oracle(ctx):
         fkconv.fk_unload_covariance(ctx.ctx, cv)
 
 
+def test_chi2_large_block(ctx):
+    """A block of 1100 points (35 row tiles: the split products take five
+    tiles per entry there) beside a small one."""
+    rng = np.random.default_rng(7)
+    Cs = []
+    for n in (1100, 40):
+        A = rng.normal(size=(n, n))
+        Cs.append(A @ A.T + n * np.eye(n))
+    Ntot = 1140
+    R = 16
+    sig = f32(rng.normal(size=(Ntot, R)) * 3)
+    D = rng.normal(size=Ntot)
+    cv = fkconv.fk_load_covariance(ctx.ctx, Cs)
+    chi, d = fkconv.fk_chi2(ctx.ctx, cv, torch.from_numpy(sig.astype(np.float32)).cuda(),
+                            torch.from_numpy(D).cuda())
+    torch.cuda.synchronize()
+    ref, dref = oracle.chi2([oracle.cholesky(C) for C in Cs], sig, D)
+    e = float(np.max(np.abs(chi.cpu().numpy() - ref) / np.abs(ref)))
+    eg = oracle.normwise_rel(d.cpu().double().numpy(), dref)
+    say(f"chi2 large block: rel err {e:.2e}, gradient (FP32 output) {eg:.2e}")
+    assert e < 1e-10
+    assert eg < 1e-6
+    fkconv.fk_unload_covariance(ctx.ctx, cv)
+
+
 def test_not_positive_definite(ctx):
     C = np.eye(5)
     C[3, 3] = -1.0
