@@ -110,15 +110,20 @@ __global__ void __launch_bounds__(256)
 }
 
 // Split products.  A work entry {rt, t0, t1, slot} (slot = the entry's
-// index in its list) asks for the partial
-// product of row tile rt (32 rows of its block) over the k tiles [t0, t1):
+// index in its list) asks for the partial product of row tile rt (32 rows
+// of its block) over the k tiles [t0, t1):
 //   lower: P = M[rows, k] e[k, cols]        (k tiles up to the diagonal)
 //   upper: P = M[i, rows]^T y[i, cols]      (i tiles from the diagonal on)
 // written to slot [32][kRpMax].  The entries of one row tile are added in
 // list order by split_reduce_kernel, so the result is a fixed-order sum.
-// Each workgroup computes 32 rows x 32 columns with 256 threads (4 rows per
-// thread); the tiles of the next k step are read into registers while the
-// current ones are multiplied.
+// A workgroup computes 32 rows x 32 columns on the FP64 matrix cores: wave
+// (wr, wc) owns the 16 x 16 quarter (rows 16 wr.., columns 16 wc..) and
+// steps through k four at a time with v_mfma_f64_16x16x4f64 (lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds rows
+// l / 16 + 4 v, v = 0..3, of column l % 16 of the result: unlike the FP32
+// form, whose rows are 4 (l / 16) + v).  The tiles of the next k step are
+// read into registers while the current ones are multiplied.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <bool UPPER>
 __global__ void __launch_bounds__(256)
     trmm_split_kernel(const int4 *__restrict__ work, const int32_t *__restrict__ rt_block,
@@ -127,8 +132,8 @@ __global__ void __launch_bounds__(256)
                       const double *__restrict__ M, const float *__restrict__ sigma,
                       const double *__restrict__ data, const double *__restrict__ y, int R,
                       int c0, int ncols, double *__restrict__ spart) {
-  __shared__ double sm[kCT][kCT + 1];
-  __shared__ double so[kCT][kCT + 1];
+  __shared__ double sm[kCT][kCT + 1];  // lower: M[r0 + r][k0 + k]; upper: M[k0 + k][r0 + r]
+  __shared__ double so[kCT][kCT + 1];  // operand [k][column]
   const int4 wk = work[blockIdx.x];
   const int rt = wk.x, t0 = wk.y, t1 = wk.z, slot = wk.w;
   const int b = rt_block[rt], r0 = rt_row[rt];
@@ -136,9 +141,7 @@ __global__ void __launch_bounds__(256)
   const double *m = M + off[b];
   const int base = roff[b];
   const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;
-  const int col = blockIdx.y * kCT + tc;
-  // this thread's four elements of each 32 x 32 tile: (i, cc) with
-  // i = threadIdx.x / 32 + 8 q
+  // this thread's four elements of each 32 x 32 tile: (tr + 8 q, tc)
   double vm[4], vo[4];
   auto fetch = [&](int t) {
     const int k0 = t * kCT;
@@ -160,7 +163,10 @@ __global__ void __launch_bounds__(256)
       vo[q] = v;
     }
   };
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
   fetch(t0);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
@@ -171,17 +177,17 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     if (t + 1 < t1) fetch(t + 1);
-#pragma unroll 4
-    for (int kk = 0; kk < kCT; ++kk) {
-      const double ov = so[kk][tc];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        acc[q] += (UPPER ? sm[kk][4 * tr + q] : sm[4 * tr + q][kk]) * ov;
+    for (int ks = 0; ks < kCT; ks += 4) {
+      const int k = ks + lk, row = 16 * wr + li;
+      const double a = UPPER ? sm[k][row] : sm[row][k];
+      const double bv = so[k][16 * wc + li];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
     }
   }
-  double *dst = spart + (size_t)slot * kCT * kRpMax;
+  double *dst = spart + (size_t)slot * kCT * kRpMax + blockIdx.y * kCT + 16 * wc + li;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) dst[(size_t)(4 * tr + q) * kRpMax + col] = acc[q];
+  for (int v = 0; v < 4; ++v) dst[(size_t)(16 * wr + lk + 4 * v) * kRpMax] = acc[v];
 }
 
 // Sum of the entries of each row tile in list order.  Lower: y and the
