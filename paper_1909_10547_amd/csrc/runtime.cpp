@@ -412,7 +412,9 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
   }
 
   // ---- streaming DIS forward: each table's blocks in ranges of about
-  // 1/(2 ncu) of all blocks, one workgroup per range
+  // 1/(8 ncu) of all blocks, one workgroup per range (several workgroups
+  // share a compute unit: measured on a 2 GiB set, ranges of 1/(8 ncu) read
+  // 5.9 TB/s, 1/(2 ncu) 5.1, 1/(32 ncu) 4.9)
   std::vector<DisGroupRef> dgroups;
   std::vector<DisStreamWG> dwgs;
   p.dis_chunk = 0;
@@ -421,7 +423,7 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     long total_blk = 0;
     for (auto *t : ts) total_blk += (t->N + 15) / 16;
     const int target =
-        (int)std::max<long>(1, std::min<long>(kDisStreamMaxBlk, (total_blk + 2 * ncu - 1) / (2 * ncu)));
+        (int)std::max<long>(1, std::min<long>(kDisStreamMaxBlk, (total_blk + 8 * ncu - 1) / (8 * ncu)));
     for (size_t t = 0; t < ts.size(); ++t) {
       const int g0 = (int)dgroups.size();
       int ttot = 0;
