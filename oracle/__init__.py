@@ -30,10 +30,19 @@ What each function follows:
                      PDF factor to the storage format and keeps the left one
                      in FP32, which is the operand set a half-precision
                      kernel of the bilinear form consumes.
+* ``normwise_rel``, ``error_report``  the error measures every parity test
+                     gates on or reports.
 
-Pins: every function is checked in ``tests/test_oracle_*.py`` against
-invariants, closed forms, exact integer brute force, library routines for
-special cases and finite differences.  None is "parity unpinned".
+Pins (``tests/test_oracle_*.py``): invariants, closed forms, exact integer
+brute force, library routines for special cases and finite differences for
+the convolutions, gradients and chi2; hand-computed values for the error
+measures; torch's own casts for the quantisers; FP64-mode identities and
+exact integer cases for the stored-operand functions.  Planted slips in the
+C loops and in this file must each fail one of them
+(``tests/test_oracle_mutants.py``).  One modelling choice is not pinned by
+the mathematics: which factor of the bilinear form the stored-operand mode
+rounds (the right one, as the kernels do); the pins only fix that the mode
+reduces to the definition when rounding is exact.
 """
 from __future__ import annotations
 
