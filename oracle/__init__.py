@@ -30,6 +30,10 @@ What each function follows:
                      PDF factor to the storage format and keeps the left one
                      in FP32, which is the operand set a half-precision
                      kernel of the bilinear form consumes.
+* ``luminosity``, ``flat_conv``  the flattened form Table 3 times: the
+                     luminosity L[(a,b,alpha,beta), r] = f_a(x_alpha) f_b(x_beta)
+                     over the active pairs, and the plain product FK[N][K] L[K][R]
+                     (a library matmul in FP64).
 * ``normwise_rel``, ``error_report``  the error measures every parity test
                      gates on or reports.
 
@@ -177,6 +181,27 @@ def had_grad(mask, fk, pdf, gbar) -> np.ndarray:
     g = np.empty((F, X, R))
     _load().oracle_had_grad(N, F, X, _p(mask), _p(fk), R, _p(pdf), _p(gbar), _p(g))
     return g
+
+
+# ---------------------------------------------------------------------------
+# flattened form (Table 3: FK table N x K against a "PDF" K x R)
+# ---------------------------------------------------------------------------
+
+def luminosity(mask, pdf) -> np.ndarray:
+    """L[(c, alpha, beta), r] = f[a_c, alpha, r] f[b_c, beta, r] for the
+    active pairs c = (a_c, b_c) in row-major (a, b) order: [np*X*X][R]."""
+    mask, pdf = _u8(mask), _f64(pdf)
+    F, X, R = pdf.shape
+    a, b = np.nonzero(mask)
+    L = np.empty((len(a), X, X, R))
+    for c in range(len(a)):
+        L[c] = pdf[a[c]][:, None, :] * pdf[b[c]][None, :, :]
+    return L.reshape(len(a) * X * X, R)
+
+
+def flat_conv(fk_flat, lum) -> np.ndarray:
+    """out[N][R] = FK[N][K] L[K][R] in FP64."""
+    return np.matmul(_f64(fk_flat), _f64(lum))
 
 
 # ---------------------------------------------------------------------------

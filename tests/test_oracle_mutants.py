@@ -51,6 +51,8 @@ PY_MUTANTS = {
     "symmetric_part_no_transpose": ("S[:, c] += np.transpose(fk[:, idx[pb, pa]], (0, 2, 1))",
                                     "S[:, c] += fk[:, idx[pb, pa]]"),
     "bf16_one_bit_short": ('"bf16": (7, -126', '"bf16": (6, -126'),
+    "luminosity_a_b_swap": ("L[c] = pdf[a[c]][:, None, :] * pdf[b[c]][None, :, :]",
+                            "L[c] = pdf[b[c]][:, None, :] * pdf[a[c]][None, :, :]"),
 }
 
 

@@ -378,3 +378,39 @@ def test_stored_operand_mode_exact_cases():
     np.testing.assert_array_equal(oracle.had_quantized(ti.mask, ti.fk, fi, "bf16"), oracle.had(ti.mask, ti.fk, fi))
     di = synth.integer_dis_table(rng, F, X, 5, 3)
     np.testing.assert_array_equal(oracle.dis_quantized(di.mask, di.fk, fi, "bf16"), oracle.dis(di.mask, di.fk, fi))
+
+
+# ---------------------------------------------------------------------------
+# the flattened form of Table 3
+# ---------------------------------------------------------------------------
+
+def test_luminosity_and_flat_form_equal_eq1():
+    # FK flattened to [N][np*X*X] against the luminosity of the active pairs
+    # is Eq. (1) (the C loops of oracle.had are an independent evaluation)
+    rng = np.random.default_rng(70)
+    xg = synth.xgrid_geom(1e-7, 1.0, 7)
+    t = synth.draw_general_had_table(rng, xg, 6, npairs=11)
+    f = rng.normal(size=(14, 7, 5))
+    L = oracle.luminosity(t.mask, f)
+    assert L.shape == (11 * 49, 5)
+    out = oracle.flat_conv(t.fk.reshape(6, -1), L)
+    assert oracle.normwise_rel(out, oracle.had(t.mask, t.fk, f)) < 1e-13
+
+
+def test_luminosity_entries_and_integer_brute_force():
+    rng = np.random.default_rng(71)
+    mask = np.zeros((F, F), np.uint8)
+    mask[0, 3] = mask[2, 2] = mask[4, 1] = 1
+    f = _pdf_distinct(rng, 2)
+    L = oracle.luminosity(mask, f).reshape(3, X, X, 2)
+    # pairs in row-major order: (0,3), (2,2), (4,1)
+    for c, (a, b) in enumerate([(0, 3), (2, 2), (4, 1)]):
+        for al in range(X):
+            for be in range(X):
+                np.testing.assert_array_equal(L[c, al, be], f[a, al] * f[b, be])
+    A = rng.integers(-9, 10, size=(4, 13)).astype(float)
+    B = rng.integers(-9, 10, size=(13, 3)).astype(float)
+    out = oracle.flat_conv(A, B)
+    for i in range(4):
+        for r in range(3):
+            assert out[i, r] == sum(int(A[i, k]) * int(B[k, r]) for k in range(13))
