@@ -49,16 +49,29 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters():
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source; else None."""
+def counters():
+    """The committed rocprofv3 counter summary of the forward kernel, if it
+    was taken on the current kernel source and planner; else None."""
     try:
         d = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
     if d.get("kernel_sha256_16") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+def traffic_from_counters():
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated), or None."""
+    d = counters()
+    return d.get("hbm_bytes_per_launch") if d else None
+
+
+def mfma_from_counters():
+    """MFMA busy fraction of the forward kernel from SQ_VALU_MFMA_BUSY_CYCLES
+    (summed over SIMDs) / (GRBM_GUI_ACTIVE of one XCD x SIMDs), or None."""
+    d = counters()
+    return d.get("mfma") if d else None
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -134,6 +147,10 @@ def main() -> int:
                     help="only load the BF16 tables and run the BF16 hadronic adjoint (for profiler runs)")
     ap.add_argument("--profile-dis", action="store_true",
                     help="only the DIS bandwidth set, BF16, R=1 (for profiler runs)")
+    ap.add_argument("--profile-nrep", type=int, default=0,
+                    help="replica count of the --profile-bf16/--profile-adj runs (default: the workload's)")
+    ap.add_argument("--profile-f32", action="store_true",
+                    help="with --profile-bf16/--profile-adj: load and run the FP32 tables instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 1 GiB three times (HBM byte-counter calibration)")
     args = ap.parse_args()
@@ -181,7 +198,14 @@ def main() -> int:
     pdf64 = w.pdf(R).astype(np.float32).astype(np.float64)
     c = fkconv.Context(0)
     t0 = time.perf_counter()
-    hb = [c.load(t, "bf16") for t in tabs]
+    if args.profile_bf16 or args.profile_adj:
+        fmt = "f32" if args.profile_f32 else "bf16"
+        hb = [c.load(t, fmt) for t in tabs]
+        if args.profile_nrep:
+            R = args.profile_nrep
+            pdf64 = w.pdf(R).astype(np.float32).astype(np.float64)
+    else:
+        hb = [c.load(t, "bf16") for t in tabs]
     gb = fkconv.fk_group_create(c.ctx, hb)
     if args.profile_bf16:
         x = torch.from_numpy(pdf64.astype(np.float32)).cuda()
@@ -282,52 +306,54 @@ def main() -> int:
             "algorithmic_bytes_per_launch": bytes_alg,
             "kernel_ms": kern_ms,
             "mfma_tflops": flops_alg / (kern_ms * 1e-3) / 1e12,
-            "mfma_frac": flops_alg / (kern_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+            "mfma_frac_algorithmic": flops_alg / (kern_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+            "mfma_counters": mfma_from_counters(),
         },
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt_b.items() if v[1]},
     }
 
     if not args.no_cpu_baseline:
         import oracle
-        log("cpu baseline (FP64 oracle on a sample)")
-        # calibrate on two datapoints, then take an evenly spread sample
+        log("cpu baseline: the FP64 oracle on every datapoint (errors per dataset)")
+        # calibrate on two datapoints; the whole workload when it fits in
+        # about four times the sample budget, else evenly spaced rows
         t0 = time.perf_counter()
         oracle.had(tabs[0].mask, tabs[0].fk[:2], pdf64)
         per_dp = (time.perf_counter() - t0) / 2
-        k = max(1, int(args.cpu_seconds / per_dp / len(tabs)))
-        rows, refs, gotb, gotf, nsamp = [], [], [], [], 0
-        off = 0
+        whole = per_dp * Ntot <= 4 * args.cpu_seconds
+        k = Ntot if whole else max(1, int(args.cpu_seconds / per_dp / len(tabs)))
+        refs, sels, nsamp, off = [], [], 0, 0
+        per_ds = []
         t0 = time.perf_counter()
-        sels = []
-        for t in tabs:
-            sel = np.unique(np.linspace(0, t.ndata - 1, min(k, t.ndata)).astype(int))
+        for d, t in enumerate(tabs):
+            sel = np.arange(t.ndata) if whole else np.unique(np.linspace(0, t.ndata - 1, min(k, t.ndata)).astype(int))
             sels.append(sel)
-            refs.append(oracle.had(t.mask, t.fk[sel], pdf64))
-            gotb.append(yb[off + sel])
-            gotf.append(yf[off + sel])
+            ref = oracle.had(t.mask, t.fk[sel], pdf64)
+            refs.append(ref)
+            per_ds.append({"dataset": d, "ndata": t.ndata, "rows": int(len(sel)),
+                           "bf16": normwise(yb[off + sel], ref), "fp32": normwise(yf[off + sel], ref)})
             nsamp += len(sel)
             off += t.ndata
         passes = 1
-        # when the sample is the whole workload and finished early, repeat it
+        # when the sample finished early, repeat it
         while time.perf_counter() - t0 < 0.8 * args.cpu_seconds:
             for t, sel in zip(tabs, sels):
                 oracle.had(t.mask, t.fk[sel], pdf64)
             passes += 1
         el = time.perf_counter() - t0
-        ref = np.concatenate(refs)
         result["cpu_baseline"] = {
             "value": passes * nsamp * R / el, "unit": "datapoint*replicas/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{nsamp} of {Ntot} datapoints (evenly spaced in every dataset) x {R} replicas, FP64, "
-                      f"{passes} pass(es) in {el:.1f}s",
+            "sample": (f"all {Ntot} datapoints" if whole else f"{nsamp} of {Ntot} datapoints (evenly spaced in "
+                       "every dataset)") + f" x {R} replicas, FP64, {passes} pass(es) in {el:.1f}s",
         }
-        # the same oracle on one thread, on the first datasets' sample rows
+        # the same oracle on one thread, on the first datasets' rows
         nth = oracle.num_threads()
         oracle.set_num_threads(1)
         t0 = time.perf_counter()
         n1 = 0
         for t, sel in zip(tabs, sels):
-            sel1 = sel[: max(1, len(sel) // 8)]
+            sel1 = sel[: max(1, len(sel) // 32)]
             oracle.had(t.mask, t.fk[sel1], pdf64)
             n1 += len(sel1)
             if time.perf_counter() - t0 > 0.5 * args.cpu_seconds:
@@ -336,9 +362,19 @@ def main() -> int:
         oracle.set_num_threads(nth)
         result["cpu_baseline"]["value_1thread"] = n1 * R / el1
         result["cpu_baseline"]["sample_1thread"] = f"{n1} datapoints x {R} replicas, FP64, 1 thread, {el1:.1f}s"
+        gotb = np.concatenate([yb[o + s_] for o, s_ in zip(np.cumsum([0] + [t.ndata for t in tabs]), sels)])
+        gotf = np.concatenate([yf[o + s_] for o, s_ in zip(np.cumsum([0] + [t.ndata for t in tabs]), sels)])
+        ref = np.concatenate(refs)
+        worst_b = max(e["bf16"] for e in per_ds)
         result["error"].update({
-            "bf16_vs_fp64_sample_normwise": normwise(np.concatenate(gotb), ref),
-            "fp32_vs_fp64_sample_normwise": normwise(np.concatenate(gotf), ref),
+            "rows_vs_fp64": "all rows" if whole else "evenly spaced rows of every dataset",
+            "bf16_vs_fp64_normwise_all": normwise(gotb, ref),
+            "fp32_vs_fp64_normwise_all": normwise(gotf, ref),
+            "bf16_vs_fp64_max_over_datasets": worst_b,
+            "fp32_vs_fp64_max_over_datasets": max(e["fp32"] for e in per_ds),
+            "per_dataset": per_ds,
+            "gate": "normwise per replica column, max over columns, per dataset: bf16 <= 5e-3, fp32 <= 1e-5",
+            "gate_met": bool(worst_b <= 5e-3 and max(e["fp32"] for e in per_ds) <= 1e-5),
         })
         try:
             result["cpu_baseline"]["cpu_model"] = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
@@ -349,7 +385,11 @@ def main() -> int:
     if not args.no_peaks:
         log("measured ceilings: HBM copy, BF16 GEMM")
         pk = measured_peaks(torch)
+        pk["mfma_bf16_register_tflops"] = fkconv.fk_measure_mfma_peak(c.ctx)
+        pk["note"] += "; register-only v_mfma_f32_16x16x32_bf16 loop (fk_measure_mfma_peak)"
         result["measured_peaks"] = pk
+        result["roofline"]["mfma_frac_of_register_peak"] = (result["roofline"]["mfma_tflops"] /
+                                                            pk["mfma_bf16_register_tflops"])
         result["roofline"]["frac_of_measured"] = achieved / pk["hbm_copy_gbs"]
     if not args.no_rsweep:
         log("replica sweep")
@@ -377,11 +417,15 @@ def main() -> int:
 def serving(c, w, had_tabs, args, torch, fkconv, synth):
     """Continuous batching: the table catalogue of the serving workload (the
     20 DIS and 10 hadronic datasets plus two DIS and two hadronic tables with
-    N = 2000), BF16 with FP32 fallback copies; requests pick a table uniformly
-    and R uniformly from {1, 4, 16, 100}; 20% ask for FP32.  Capacity is
-    measured closed-loop (everything submitted at once), then Poisson streams
-    at fractions of it; latency = submit -> completion seen by the loop."""
-    import threading
+    N = 2000), BF16 with FP32 fallback copies; each BF16 table is probed
+    against its fallback on a 100-replica batch and routed to it when the
+    error is above 5e-3; requests pick a table uniformly and R uniformly
+    from {1, 4, 16, 100}; 20% ask for FP32.  Capacity is measured
+    closed-loop (everything submitted at once), then Poisson streams at
+    fractions of it; latency = submit -> completion seen by the loop.
+    Afterwards every request of the last stream is re-run alone (bitwise
+    equality is required) and its error is measured."""
+    import oracle
     sw = synth.serving_workload(1.0)
     cat = list(sw.catalogue())
     hb, hf = [], []
@@ -393,6 +437,8 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
     kinds = [k for k, _ in cat]
     pools = {R: [torch.from_numpy(sw.request_pdf(R, k).astype(np.float32)).cuda() for k in range(4)]
              for R in sw.rep_choices}
+    probe = [fkconv.fk_table_probe(c.ctx, h, pools[100][0], tol=5e-3) for h in hb]
+    routed = [i for i, e in enumerate(probe) if e > 5e-3]
     fkconv.fk_serve_start(c.ctx, nslots=256, nstreams=4, request_budget_bytes=512 << 20)
     rng = np.random.default_rng(4)
 
@@ -421,7 +467,10 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
         pend = set(range(nreq))
         while pend:
             for i in list(pend):
-                if fkconv.fk_poll(c.ctx, tickets[i]) >= fkconv.FK_DONE:
+                st = fkconv.fk_poll(c.ctx, tickets[i])
+                if st == fkconv.FK_FAILED:
+                    raise RuntimeError(f"serving request {i} failed")
+                if st == fkconv.FK_DONE:
                     pend.discard(i)
         wall = time.perf_counter() - t0
         lat = np.array([(lambda a, b, d: (d - a) * 1e-6)(*fkconv.fk_ticket_times(c.ctx, t)) for t in tickets])
@@ -430,7 +479,8 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
                 "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99))}, \
             (tab, Rs, prec, outs, pseed)
 
-    res = {}
+    res = {"probe": {"tol": 5e-3, "max_err": float(max(probe)), "routed_to_fp32": len(routed),
+                     "tables": len(cat)}}
     nreq = 2000 if args.serve_quick else 10000
     cap, sample = run(nreq, None)
     res["closed_loop"] = cap
@@ -439,14 +489,52 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
         r, sample = run(nreq, f * cap["req_per_s"])
         res[f"rate_{f:g}x"] = r
     fkconv.fk_serve_stop(c.ctx)
-    # alone-vs-mix: re-run a sample of the last stream's requests alone
+
+    # every request of the last stream: alone run (bitwise) and error.  The
+    # reference of a request is its FP32 alone run on the GPU; the FP32
+    # runs of every distinct (table, PDF batch) are checked against the FP64
+    # oracle (DIS: every row; hadronic: 16 evenly spaced rows).
     tab, Rs, prec, outs, pseed = sample
-    same = 0
-    for i in range(0, len(outs), max(1, len(outs) // 200)):
-        h = hf[tab[i]] if prec[i] == fkconv.FK_F32 else hb[tab[i]]
-        fn = fkconv.fk_conv_had if kinds[tab[i]] == "had" else fkconv.fk_conv_dis
-        same += int(torch.equal(fn(c.ctx, h, pools[int(Rs[i])][int(pseed[i]) % 4]), outs[i]))
-    res["alone_equals_mix"] = f"{same} of {len(range(0, len(outs), max(1, len(outs) // 200)))} sampled requests bitwise equal"
+    ref32, alone = {}, {}
+    differ = 0
+    err_b, err_f = [], []
+    for i in range(len(outs)):
+        key = (int(tab[i]), int(Rs[i]), int(pseed[i]) % 4)
+        x = pools[key[1]][key[2]]
+        fn = fkconv.fk_conv_had if kinds[key[0]] == "had" else fkconv.fk_conv_dis
+        if key not in ref32:
+            ref32[key] = fn(c.ctx, hf[key[0]], x)
+            alone[key] = fn(c.ctx, hb[key[0]] if key[0] not in routed else hf[key[0]], x)
+        want = ref32[key] if prec[i] == fkconv.FK_F32 else alone[key]
+        differ += int(not torch.equal(want, outs[i]))
+        r = ref32[key]
+        num = ((outs[i].double() - r.double()) ** 2).sum(0).sqrt()
+        den = (r.double() ** 2).sum(0).sqrt()
+        e = float((num / den).max())
+        (err_f if prec[i] == fkconv.FK_F32 else err_b).append(e)
+    if differ:
+        raise RuntimeError(f"serving: {differ} of {len(outs)} requests differ from their alone runs")
+    ref_err = 0.0
+    for (ti, R, k), y in ref32.items():
+        t = cat[ti][1]
+        pdf = pools[R][k].double().cpu().numpy()
+        if kinds[ti] == "had":
+            sel = np.unique(np.linspace(0, t.ndata - 1, 16).astype(int))
+            ref = oracle.had(t.mask, t.fk[sel], pdf)
+        else:
+            sel = np.arange(t.ndata)
+            ref = oracle.dis(t.mask, t.fk, pdf)
+        ref_err = max(ref_err, oracle.normwise_rel(y.double().cpu().numpy()[sel], ref))
+    res["alone_equals_mix"] = f"all {len(outs)} requests of the last stream bitwise equal to their alone runs"
+    res["error"] = {
+        "bf16_requests_max_normwise": float(max(err_b)) if err_b else None,
+        "bf16_requests_over_5e-3": int(sum(e > 5e-3 for e in err_b)),
+        "fp32_requests_max_normwise": float(max(err_f)) if err_f else None,
+        "requests": len(outs),
+        "reference": "each request's FP32 alone run; FP32 vs the FP64 oracle over every distinct "
+                     "(table, PDF batch): DIS every row, hadronic 16 evenly spaced rows",
+        "fp32_reference_vs_fp64_max_normwise": ref_err,
+    }
     for h in hb + hf:
         fkconv.fk_unload_table(c.ctx, h)
     return res

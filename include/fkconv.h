@@ -29,7 +29,9 @@
  *      PDF f       [nflav][nx][nrep]   float32, device
  *      observables [ndata][nrep]       float32, device
  *  - Calls on one table/group handle use that handle's scratch memory, so
- *    they must be ordered on one stream (the serving loop has its own).
+ *    they must be ordered on one stream.  The serving loop gives each of its
+ *    streams private scratch per table, so direct calls and served requests
+ *    on the same table may overlap.
  */
 #ifndef FKCONV_H
 #define FKCONV_H
@@ -82,6 +84,18 @@ const char *fk_last_error(const fk_ctx *ctx);
 
 /* Bytes currently charged to the budget, and the budget itself. */
 fk_status fk_memory(const fk_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* Context options.
+ *  FK_OPT_KERNELS  FK_KERNELS_STREAM (default): the streaming hadronic
+ *                  forward/adjoint and DIS forward kernels where a plan has
+ *                  them; FK_KERNELS_ITEM: the persistent / per-item kernels
+ *                  (for comparisons: the two families sum in different
+ *                  orders, so results agree to rounding, not bitwise).
+ * Takes effect for calls issued after it returns.  FK_E_ARG for an unknown
+ * option or value. */
+enum { FK_OPT_KERNELS = 1 };
+enum { FK_KERNELS_STREAM = 0, FK_KERNELS_ITEM = 1 };
+fk_status fk_set_option(fk_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- tables (Section 3: one FK table per dataset) --------------------- */
 
@@ -205,6 +219,14 @@ fk_status fk_timing_enable(fk_ctx *ctx, int32_t enable);
  * read (host arrays of FK_K_COUNT entries); then reset. */
 fk_status fk_timing_read(fk_ctx *ctx, double *total_ms, int64_t *launches);
 
+/* Measured ceiling of the matrix cores: a kernel of independent
+ * v_mfma_f32_16x16x32_bf16 chains on register operands (no memory traffic),
+ * 32 waves per compute unit, ``iters`` rounds of eight MFMAs per wave; the
+ * best of three timed runs (after one warm-up) in dense BF16 TFLOP/s.  Runs
+ * on the legacy default stream and waits for it.  The denominator of the
+ * roofline fractions is the datasheet peak; this is the achievable one. */
+fk_status fk_measure_mfma_peak(fk_ctx *ctx, int32_t iters, double *tflops);
+
 /* ---- serving: continuous batching of convolution requests --------------
  * Requests name a resident table, carry their own PDF batch and output,
  * and are admitted as request slots and the request-buffer budget allow.
@@ -215,11 +237,18 @@ fk_status fk_timing_read(fk_ctx *ctx, double *total_ms, int64_t *launches);
 typedef struct {
   fk_table table;     /* a table (not a group) */
   int32_t nrep;       /* replicas of this request, >= 1 */
-  int32_t precision;  /* FK_BF16: the table as loaded; FK_F32: its FP32
-                         fallback table if one is linked (else as loaded) */
+  int32_t precision;  /* FK_BF16: the table as loaded, or its FP32 fallback
+                         when fk_table_probe found its error above the
+                         tolerance; FK_F32: its FP32 fallback table if one
+                         is linked (else as loaded) */
   const float *pdf;   /* device [nflav][nx][nrep], valid until DONE/FAILED */
   float *out;         /* device [ndata][nrep], written when DONE */
   uint64_t tag;       /* caller data, unused by the library */
+  void *ready;        /* hipEvent_t or NULL: the pass reads ``pdf`` only
+                         after this event has completed (record it on the
+                         stream that produces the PDF); it must stay valid
+                         until the request is DONE or FAILED.  With NULL the
+                         PDF must be complete when fk_submit is called. */
 } fk_request;
 
 /* Start the serving loop: ``nslots`` requests may be in flight at once,
@@ -233,12 +262,26 @@ fk_status fk_serve_stop(fk_ctx *ctx);
 /* Link an FP32 copy of a table, used for requests with precision FK_F32. */
 fk_status fk_table_set_fallback(fk_ctx *ctx, fk_table table, fk_table fallback);
 
+/* Probe a reduced-precision table (BF16 or FP8) against its linked FP32
+ * fallback on a caller PDF batch: both are convolved on ``stream`` and the
+ * normwise error max_r ||y_r - y32_r||_2 / ||y32_r||_2 is computed on the
+ * device (FP64 sums) and returned in *err (the call waits for the stream).
+ * When *err > tol, served requests that ask for the table's own format run
+ * on the fallback from then on (FP32 differs from the FP64 definition by
+ * about 1e-7, far below any tolerance this is used with); otherwise they
+ * run on the table.  The tolerance the paper's setting suggests for BF16 is
+ * 5e-3.  The call allocates its two outputs and frees them before it
+ * returns.  FK_E_STATE when no fallback is linked. */
+fk_status fk_table_probe(fk_ctx *ctx, fk_table table, const float *pdf, int32_t nrep,
+                         double tol, double *err, void *stream);
+
 /* Queue a request; never blocks.  FK_E_QUEUE_FULL when the queue is full,
  * FK_E_TOO_LARGE when the request could never fit the request budget. */
 fk_status fk_submit(fk_ctx *ctx, const fk_request *req, fk_ticket *out);
 
-/* State of a ticket: FK_QUEUED, FK_RUNNING, FK_DONE or FK_FAILED.  Ticket
- * records are kept until fk_serve_stop. */
+/* State of a ticket: FK_QUEUED, FK_RUNNING, FK_DONE or FK_FAILED.  The
+ * record of a finished ticket is kept until 65536 later requests have
+ * finished (then FK_E_HANDLE), or until fk_serve_stop. */
 fk_status fk_poll(fk_ctx *ctx, fk_ticket ticket, int32_t *state);
 
 /* Timing of a finished ticket in nanoseconds of the host steady clock:

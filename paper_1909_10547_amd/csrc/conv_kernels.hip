@@ -1395,4 +1395,37 @@ hipError_t launch_adj_reduce(const ConvLaunch &L, int nrows_out, const int32_t *
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Error of a reduced-precision result against a reference, per replica
+// column: out[2 r] = sum_i (y[i,r] - ref[i,r])^2, out[2 r + 1] = sum_i
+// ref[i,r]^2, in FP64.  One wave per column, lanes stride the rows, a fixed
+// tree across the wave.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+    col_err_kernel(const float *__restrict__ y, const float *__restrict__ ref, int N, int R,
+                   double *__restrict__ out) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  double d2 = 0.0, r2 = 0.0;
+  for (int i = lane; i < N; i += 64) {
+    const double a = ref[(size_t)i * R + r], b = y[(size_t)i * R + r];
+    d2 += (b - a) * (b - a);
+    r2 += a * a;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o);
+    r2 += __shfl_xor(r2, o);
+  }
+  if (lane == 0) {
+    out[2 * r] = d2;
+    out[2 * r + 1] = r2;
+  }
+}
+
+hipError_t launch_col_err(const float *y, const float *ref, int N, int R, double *out,
+                          hipStream_t s) {
+  if (N <= 0 || R <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(col_err_kernel, dim3(R), dim3(64), 0, s, y, ref, N, R, out);
+  return hipGetLastError();
+}
+
 }  // namespace fk

@@ -198,6 +198,11 @@ hipError_t launch_adj_reduce(const ConvLaunch &L, int nrows_out, const int32_t *
                              const int64_t *entry_off, const float *apart, int accumulate,
                              float *g);
 
+// Per replica column r: out[2r] = sum_i (y - ref)^2, out[2r+1] = sum_i ref^2
+// (FP64), for y and ref [N][R].
+hipError_t launch_col_err(const float *y, const float *ref, int N, int R, double *out,
+                          hipStream_t s);
+
 // chi2 (chi2_kernels.hip)
 hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off, double *d_a,
                            double *d_linv, int32_t *d_flag, int maxn, hipStream_t s);

@@ -673,6 +673,9 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     p.d_fstage = (float *)d;
   }
   p.grid_fwd = 2 * ncu;
+  p.bop_units = bop;
+  p.fpart_floats = (size_t)nslots * 16 * kRpMax;
+  p.apart_floats = std::max(apart_floats, apart2_floats);
   p.bytes = 0;
   for (auto &a : p.allocs) p.bytes += a.second;
   return FK_OK;
@@ -707,14 +710,37 @@ static hipError_t timed(Timing *tm, int kind, hipStream_t s, F &&launch) {
   return e;
 }
 
+fk_status clone_forward_scratch(fk_ctx *c, const Plan &p, Plan &q,
+                                std::vector<std::pair<void *, size_t>> *track) {
+  q = p;
+  q.allocs.clear();
+  q.bytes = 0;
+  q.d_apart = nullptr;
+  q.d_wstage = nullptr;
+  void *d = nullptr;
+  fk_status st;
+  if ((st = dev_alloc(c, std::max<size_t>(p.bop_units, 1) * 16, &d, track))) return st;
+  q.d_bop = (uint4 *)d;
+  if ((st = dev_alloc(c, std::max<size_t>(p.fpart_floats, 1) * 4, &d, track))) return st;
+  q.d_fpart = (float *)d;
+  if ((st = dev_alloc(c, 64, &d, track))) return st;
+  q.d_counter = (int *)d;
+  FK_TRY_HIP(c, hipMemset(q.d_counter, 0, 64));
+  if (p.d_fstage) {
+    if ((st = dev_alloc(c, (size_t)p.F * p.X * kRpMax * 4, &d, track))) return st;
+    q.d_fstage = (float *)d;
+  }
+  return FK_OK;
+}
+
 hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hipStream_t s,
-                       Timing *tm) {
-  // FKCONV_NO_STREAM selects the persistent hadronic forward kernel (for
+                       Timing *tm, int kernels) {
+  // FK_KERNELS_ITEM selects the persistent hadronic forward kernel (for
   // comparisons; the two kernels sum in different orders).  A plan that
   // uses the stream kernel uses it for every column pass, so that a
   // request's result does not depend on the replica count it is batched
   // with: passes are cut to 112 columns when 128 do not fit its LDS.
-  const bool no_stream = std::getenv("FKCONV_NO_STREAM") != nullptr;
+  const bool no_stream = kernels == FK_KERNELS_ITEM;
   const bool stream = p.kind == FK_HAD && p.grid_stream > 0 && !no_stream;
   const bool dstream = p.kind == FK_DIS && p.dis_chunk > 0 && !no_stream;
   const int chunk = dstream ? p.dis_chunk
@@ -763,12 +789,11 @@ hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hi
 }
 
 hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int nrep, float *g,
-                        int accumulate, hipStream_t s, Timing *tm) {
+                        int accumulate, hipStream_t s, Timing *tm, int kernels) {
   // The stream adjoint (when the plan has it) runs in passes of 112 columns
-  // when 128 do not fit its LDS; FKCONV_NO_STREAM selects the per-item
+  // when 128 do not fit its LDS; FK_KERNELS_ITEM selects the per-item
   // kernel, as for the forward.
-  const bool astream = p.kind == FK_HAD && p.grid_astream > 0 &&
-                       std::getenv("FKCONV_NO_STREAM") == nullptr;
+  const bool astream = p.kind == FK_HAD && p.grid_astream > 0 && kernels != FK_KERNELS_ITEM;
   const int chunk =
       astream && !had_stream_lds_bytes(8, p.X, p.maxT_adj, kStreamAdj) ? 112 : kRpMax;
   for (int c0 = 0; c0 < nrep; c0 += chunk) {
@@ -875,6 +900,18 @@ fk_status fk_memory(const fk_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_by
   if (used_bytes) *used_bytes = ctx->used.load();
   if (budget_bytes) *budget_bytes = ctx->budget;
   return FK_OK;
+}
+
+fk_status fk_set_option(fk_ctx *ctx, int32_t option, int64_t value) {
+  if (!ctx) return FK_E_ARG;
+  if (option == FK_OPT_KERNELS) {
+    if (value != FK_KERNELS_STREAM && value != FK_KERNELS_ITEM)
+      return set_err(ctx, FK_E_ARG, "fk_set_option: FK_OPT_KERNELS takes FK_KERNELS_STREAM or "
+                     "FK_KERNELS_ITEM (got %lld)", (long long)value);
+    ctx->kernels.store((int)value);
+    return FK_OK;
+  }
+  return set_err(ctx, FK_E_ARG, "fk_set_option: unknown option %d", option);
 }
 
 fk_status fk_load_table(fk_ctx *ctx, int32_t kind, int32_t ndata, int32_t nflav, int32_t nx,
@@ -1028,6 +1065,60 @@ fk_status fk_unload_table(fk_ctx *ctx, fk_table table) {
   return FK_OK;
 }
 
+fk_status fk_table_probe(fk_ctx *ctx, fk_table table, const float *pdf, int32_t nrep, double tol,
+                         double *err, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  if (!pdf || !err || nrep < 1 || !(tol >= 0.0))
+    return set_err(ctx, FK_E_ARG, "fk_table_probe: need pdf, err, nrep >= 1 and tol >= 0");
+  *err = -1.0;
+  Plan *p = nullptr, *pf = nullptr;
+  Table *t = nullptr;
+  {
+    Guard g(ctx);
+    t = find_table(ctx, table);
+    if (!t) return set_err(ctx, FK_E_HANDLE, "fk_table_probe: %lld is not a loaded table", (long long)table);
+    if (!t->fallback || !find_table(ctx, t->fallback))
+      return set_err(ctx, FK_E_STATE, "fk_table_probe: table %lld has no FP32 fallback linked",
+                     (long long)table);
+    p = find_plan(ctx, table);
+    pf = find_plan(ctx, t->fallback);
+  }
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const hipStream_t s = (hipStream_t)stream;
+  const size_t ny = (size_t)t->N * nrep;
+  std::vector<std::pair<void *, size_t>> tmp;
+  void *d = nullptr;
+  fk_status st = dev_alloc(ctx, ny * 2 * sizeof(float) + (size_t)nrep * 2 * sizeof(double), &d, &tmp);
+  if (st) return st;
+  float *y = (float *)d, *yf = y + ny;
+  double *sums = (double *)(yf + ny);
+  const int kern = ctx->kernels.load();
+  hipError_t e = run_forward(*p, pdf, nrep, y, s, nullptr, kern);
+  if (e == hipSuccess) e = run_forward(*pf, pdf, nrep, yf, s, nullptr, kern);
+  if (e == hipSuccess) e = launch_col_err(y, yf, t->N, nrep, sums, s);
+  std::vector<double> h((size_t)nrep * 2);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), sums, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free_all(ctx, tmp);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_table_probe: %s", hipGetErrorString(e));
+  double worst = 0.0;
+  for (int r = 0; r < nrep; ++r) {
+    const double num = std::sqrt(h[2 * r]), den = std::sqrt(h[2 * r + 1]);
+    // an all-zero reference column: any nonzero result is an infinite error
+    const double v = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+    worst = std::max(worst, v);
+  }
+  {
+    Guard g(ctx);
+    if (Table *tt = find_table(ctx, table)) {
+      tt->probe_err = worst;
+      tt->route_fallback = worst > tol;
+    }
+  }
+  *err = worst;
+  return FK_OK;
+}
+
 fk_status fk_table_info(fk_ctx *ctx, fk_table table, int32_t *kind, int32_t *ndata, int32_t *nflav,
                         int32_t *nx, int32_t *store_dtype, uint64_t *device_bytes) {
   if (!ctx) return FK_E_ARG;
@@ -1065,7 +1156,7 @@ static fk_status conv_common(fk_ctx *ctx, fk_table table, int kind, const double
     }
   }
   FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  hipError_t e = run_forward(*p, pdf, nrep, out, (hipStream_t)stream, &ctx->timing);
+  hipError_t e = run_forward(*p, pdf, nrep, out, (hipStream_t)stream, &ctx->timing, ctx->kernels.load());
   if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "%s: launch failed: %s", name, hipGetErrorString(e));
   return FK_OK;
 }
@@ -1094,7 +1185,7 @@ fk_status fk_conv_backward(fk_ctx *ctx, fk_table table, const float *pdf, const 
   }
   FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
   hipError_t e = run_backward(*p, pdf, grad_out, nrep, grad_pdf, accumulate, (hipStream_t)stream,
-                              &ctx->timing);
+                              &ctx->timing, ctx->kernels.load());
   if (e != hipSuccess)
     return set_err(ctx, FK_E_HIP, "fk_conv_backward: launch failed: %s", hipGetErrorString(e));
   return FK_OK;

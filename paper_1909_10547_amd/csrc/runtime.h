@@ -32,6 +32,10 @@ struct Table {
   int64_t fallback = 0;
   int group_refs = 0;
   int busy = 0;  // serving passes in flight on this table
+  // BF16/FP8 probe against the FP32 fallback (fk_table_probe): the measured
+  // error, and whether requests for the table's own format go to the fallback
+  double probe_err = -1.0;
+  bool route_fallback = false;
   std::vector<std::pair<void *, size_t>> allocs;
 };
 
@@ -85,6 +89,8 @@ struct Plan {
   int dis_ttot_max = 0;
   int dis_chunk = 0;  // columns per pass of the DIS stream kernel; 0: not used
   int maxT_fwd = 1, maxT_adj = 1;
+  // scratch sizes (for copies of the plan with private scratch)
+  size_t bop_units = 0, fpart_floats = 0, apart_floats = 0;
   // bookkeeping
   std::vector<std::pair<void *, size_t>> allocs;
   uint64_t bytes = 0;
@@ -133,6 +139,7 @@ struct fk_ctx {
   std::map<int64_t, std::unique_ptr<fk::Cov>> covs;
   fk_serve *serve = nullptr;
   fk::Timing timing;
+  std::atomic<int> kernels{FK_KERNELS_STREAM};  // fk_set_option(FK_OPT_KERNELS)
 };
 
 namespace fk {
@@ -144,10 +151,17 @@ Plan *find_plan(fk_ctx *c, int64_t h);
 Table *find_table(fk_ctx *c, int64_t h);
 
 // Launch the forward or the adjoint of ``plan`` (no validation, no locking).
+// ``kernels`` is FK_KERNELS_STREAM or FK_KERNELS_ITEM (fk_set_option).
 hipError_t run_forward(const Plan &p, const float *pdf, int nrep, float *out, hipStream_t s,
-                       Timing *tm = nullptr);
+                       Timing *tm = nullptr, int kernels = FK_KERNELS_STREAM);
 hipError_t run_backward(const Plan &p, const float *pdf, const float *gout, int nrep, float *g,
-                        int accumulate, hipStream_t s, Timing *tm = nullptr);
+                        int accumulate, hipStream_t s, Timing *tm = nullptr,
+                        int kernels = FK_KERNELS_STREAM);
+// A copy of ``p`` that shares its descriptors and table data but owns new
+// forward scratch (tracked in ``track``), so that its forward passes can run
+// concurrently with those of ``p``.  The copy has no adjoint scratch.
+fk_status clone_forward_scratch(fk_ctx *c, const Plan &p, Plan &q,
+                                std::vector<std::pair<void *, size_t>> *track);
 int pick_nt(int ncols);
 
 }  // namespace fk

@@ -5,16 +5,20 @@
 // free: all queued requests on the same table that fit the lane's staging
 // memory are coalesced into one pass over the table (their replica columns
 // are concatenated, the GPU may only pay off for a large enough batch per
-// Section 3-4), and passes on different tables run concurrently on the
-// lanes' streams.  A table has at most one pass in flight, which keeps its
-// scratch memory private to that pass.  Every output column is computed by
-// the same arithmetic whatever the other columns of its pass are, so a
+// Section 3-4), and passes run concurrently on the lanes' streams, several
+// on one table if its requests keep arriving.  Each lane runs a table's
+// passes with scratch memory of its own (a copy of the table's plan that
+// shares the table and descriptors), so passes never share scratch with one
+// another or with direct calls.  Every output column is computed by the
+// same arithmetic whatever the other columns of its pass are, so a
 // request's result does not depend on the mix it was served in.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <thread>
 #include <unordered_map>
+
+#include <memory>
 
 #include "runtime.h"
 
@@ -44,7 +48,11 @@ struct Lane {
   bool busy = false;
   int64_t table = 0;
   std::vector<int64_t> tickets;
+  // the lane's copies of the table plans it has run, with private scratch
+  std::unordered_map<int64_t, std::unique_ptr<Plan>> plans;
 };
+
+constexpr size_t kKeepDone = 65536;  // finished ticket records kept
 
 }  // namespace
 
@@ -59,6 +67,7 @@ struct fk_serve {
   bool stop = false;
   std::deque<int64_t> queue;
   std::unordered_map<int64_t, Ticket> tickets;
+  std::deque<int64_t> finished;  // finished tickets, oldest first
   int64_t next = 1;
   int inflight = 0;
   size_t max_queue = 1 << 20;
@@ -77,8 +86,13 @@ void fk_serve::complete(Lane &lane, bool ok) {
       if (it == tickets.end()) continue;
       it->second.state = ok ? FK_DONE : FK_FAILED;
       it->second.t_done = t;
+      finished.push_back(id);
     }
     inflight -= (int)lane.tickets.size();
+    while (finished.size() > kKeepDone) {
+      tickets.erase(finished.front());
+      finished.pop_front();
+    }
   }
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -88,8 +102,9 @@ void fk_serve::complete(Lane &lane, bool ok) {
   lane.busy = false;
 }
 
-// Pick the oldest request whose table is idle and coalesce the queued
-// requests on that table into one pass.  Returns true if a pass started.
+// Pick the oldest queued request and coalesce the queued requests on its
+// table into one pass on ``lane``.  Returns true if a pass started (or a
+// request was failed).
 bool fk_serve::dispatch(Lane &lane) {
   std::vector<Ticket *> batch;
   std::vector<int64_t> ids;
@@ -101,22 +116,30 @@ bool fk_serve::dispatch(Lane &lane) {
     std::lock_guard<std::mutex> lk(mu);
     if (queue.empty() || inflight >= nslots) return false;
     std::lock_guard<std::mutex> lk2(ctx->mu);
-    for (auto qi = queue.begin(); qi != queue.end(); ++qi) {
-      Ticket &t = tickets[*qi];
-      Table *tb = find_table(ctx, t.table);
-      if (!tb) {  // unloaded behind our back: fail the request
-        t.state = FK_FAILED;
-        t.t_done = now_ns();
-        queue.erase(qi);
-        return true;
+    const int64_t id0 = queue.front();
+    Ticket &t0 = tickets[id0];
+    Table *tb = find_table(ctx, t0.table);
+    Plan *pl = tb ? find_plan(ctx, t0.table) : nullptr;
+    auto fail_front = [&]() {
+      t0.state = FK_FAILED;
+      t0.t_done = now_ns();
+      finished.push_back(id0);
+      queue.pop_front();
+      return true;
+    };
+    if (!tb || !pl) return fail_front();  // unloaded behind our back
+    auto &mine = lane.plans[t0.table];
+    if (!mine) {
+      auto q = std::make_unique<Plan>();
+      if (clone_forward_scratch(ctx, *pl, *q, &allocs) != FK_OK) {
+        lane.plans.erase(t0.table);
+        return fail_front();
       }
-      if (tb->busy) continue;
-      table = t.table;
-      tab = tb;
-      plan = find_plan(ctx, table);
-      break;
+      mine = std::move(q);
     }
-    if (!plan) return false;
+    table = t0.table;
+    tab = tb;
+    plan = mine.get();
     const size_t per_col = ((size_t)tab->F * tab->X + (size_t)tab->N) * sizeof(float);
     for (auto qi = queue.begin(); qi != queue.end();) {
       Ticket &t = tickets[*qi];
@@ -140,11 +163,15 @@ bool fk_serve::dispatch(Lane &lane) {
     inflight += (int)batch.size();
     tab->busy++;
   }
-  // enqueue: gather the PDF columns, one pass, scatter the outputs
+  // enqueue: wait for the producers of the PDFs, gather the PDF columns,
+  // one pass, scatter the outputs
   const int F = tab->F, X = tab->X, N = tab->N;
   float *pdf = (float *)lane.arena;
   float *out = pdf + (size_t)F * X * rtot;
   hipError_t e = hipSuccess;
+  for (Ticket *b : batch)
+    if (e == hipSuccess && b->req.ready)
+      e = hipStreamWaitEvent(lane.stream, (hipEvent_t)b->req.ready, 0);
   size_t col = 0;
   for (Ticket *b : batch) {
     const size_t w = (size_t)b->req.nrep * sizeof(float);
@@ -153,7 +180,7 @@ bool fk_serve::dispatch(Lane &lane) {
                            hipMemcpyDeviceToDevice, lane.stream);
     col += b->req.nrep;
   }
-  if (e == hipSuccess) e = run_forward(*plan, pdf, (int)rtot, out, lane.stream);
+  if (e == hipSuccess) e = run_forward(*plan, pdf, (int)rtot, out, lane.stream, nullptr, ctx->kernels.load());
   col = 0;
   for (Ticket *b : batch) {
     const size_t w = (size_t)b->req.nrep * sizeof(float);
@@ -286,7 +313,8 @@ fk_status fk_submit(fk_ctx *ctx, const fk_request *req, fk_ticket *out) {
     Table *tb = find_table(ctx, req->table);
     if (!tb) return set_err(ctx, FK_E_HANDLE, "fk_submit: %lld is not a loaded table", (long long)req->table);
     t.table = req->table;
-    if (req->precision == FK_F32 && tb->dtype != FK_F32 && tb->fallback) t.table = tb->fallback;
+    if (tb->fallback && tb->dtype != FK_F32 && (req->precision == FK_F32 || tb->route_fallback))
+      t.table = tb->fallback;
     t.need = ((size_t)tb->F * tb->X + (size_t)tb->N) * sizeof(float) * (size_t)req->nrep;
   }
   if (t.need > s->lanes[0].bytes)

@@ -33,10 +33,15 @@ _PI32 = ctypes.POINTER(ctypes.c_int32)
 _PU64 = ctypes.POINTER(ctypes.c_uint64)
 
 
+FK_OPT_KERNELS = 1
+FK_KERNELS_STREAM, FK_KERNELS_ITEM = 0, 1
+
+
 class fk_request(ctypes.Structure):
     _fields_ = [("table", ctypes.c_int64), ("nrep", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("pdf", ctypes.c_void_p),
-                ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+                ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64),
+                ("ready", ctypes.c_void_p)]
 
 
 SIGNATURES = {
@@ -44,6 +49,7 @@ SIGNATURES = {
     "fk_destroy": (_I32, [_P]),
     "fk_last_error": (ctypes.c_char_p, [_P]),
     "fk_memory": (_I32, [_P, _PU64, _PU64]),
+    "fk_set_option": (_I32, [_P, _I32, _I64]),
     "fk_load_table": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _PI64]),
     "fk_unload_table": (_I32, [_P, _I64]),
     "fk_group_create": (_I32, [_P, _I32, _P, _PI64]),
@@ -56,9 +62,11 @@ SIGNATURES = {
     "fk_chi2": (_I32, [_P, _I64, _P, _P, _I32, _P, _P, _P]),
     "fk_timing_enable": (_I32, [_P, _I32]),
     "fk_timing_read": (_I32, [_P, _P, _P]),
+    "fk_measure_mfma_peak": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_double)]),
     "fk_serve_start": (_I32, [_P, _I32, _I32, _U64]),
     "fk_serve_stop": (_I32, [_P]),
     "fk_table_set_fallback": (_I32, [_P, _I64, _I64]),
+    "fk_table_probe": (_I32, [_P, _I64, _P, _I32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P]),
     "fk_submit": (_I32, [_P, ctypes.POINTER(fk_request), _PI64]),
     "fk_poll": (_I32, [_P, _I64, _PI32]),
     "fk_ticket_times": (_I32, [_P, _I64, _PU64, _PU64, _PU64]),
@@ -145,6 +153,10 @@ def fk_memory(ctx):
     u, b = ctypes.c_uint64(), ctypes.c_uint64()
     _check(ctx, lib().fk_memory(ctx, ctypes.byref(u), ctypes.byref(b)))
     return u.value, b.value
+
+
+def fk_set_option(ctx, option: int, value: int):
+    _check(ctx, lib().fk_set_option(ctx, option, value))
 
 
 # ---------------------------------------------------------------------------
@@ -290,6 +302,13 @@ def fk_timing_read(ctx) -> dict:
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_KINDS)}
 
 
+def fk_measure_mfma_peak(ctx, iters: int = 20000) -> float:
+    """Dense BF16 TFLOP/s of a register-only MFMA loop on this device."""
+    v = ctypes.c_double()
+    _check(ctx, lib().fk_measure_mfma_peak(ctx, iters, ctypes.byref(v)))
+    return v.value
+
+
 # ---------------------------------------------------------------------------
 # serving
 # ---------------------------------------------------------------------------
@@ -300,24 +319,50 @@ def fk_serve_start(ctx, nslots: int = 64, nstreams: int = 4, request_budget_byte
 
 def fk_serve_stop(ctx):
     _check(ctx, lib().fk_serve_stop(ctx))
+    for k in [k for k in _ready_events if k[0] == ctx.value]:
+        del _ready_events[k]
 
 
 def fk_table_set_fallback(ctx, table: int, fallback: int):
     _check(ctx, lib().fk_table_set_fallback(ctx, table, fallback))
 
 
-def fk_submit(ctx, table: int, pdf, out, precision: int = FK_BF16, tag: int = 0) -> int:
+def fk_table_probe(ctx, table: int, pdf, tol: float = 5e-3, stream=None) -> float:
+    """Error of ``table`` against its linked FP32 fallback on ``pdf``; served
+    requests for the table's own format go to the fallback when it exceeds
+    ``tol``."""
+    err = ctypes.c_double()
+    _check(ctx, lib().fk_table_probe(ctx, table, _dptr(pdf, "f32", "pdf"), pdf.shape[2], tol,
+                                     ctypes.byref(err), _stream(stream)))
+    return err.value
+
+
+# events of submitted requests, kept alive until their ticket is finished
+_ready_events = {}
+
+
+def fk_submit(ctx, table: int, pdf, out, precision: int = FK_BF16, tag: int = 0,
+              stream=None) -> int:
+    """Queue a request.  An event recorded on ``stream`` (default: the current
+    torch stream) orders the pass after the work that produced ``pdf``."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    ev = torch.cuda.Event()
+    ev.record(s)
     req = fk_request(table=table, nrep=pdf.shape[2], precision=precision,
                      pdf=_dptr(pdf, "f32", "pdf").value, out=_dptr(out, "f32", "out").value,
-                     tag=tag)
+                     tag=tag, ready=ctypes.c_void_p(ev.cuda_event))
     t = ctypes.c_int64()
     _check(ctx, lib().fk_submit(ctx, ctypes.byref(req), ctypes.byref(t)))
+    _ready_events[(ctx.value, t.value)] = ev
     return t.value
 
 
 def fk_poll(ctx, ticket: int) -> int:
     s = ctypes.c_int32()
     _check(ctx, lib().fk_poll(ctx, ticket, ctypes.byref(s)))
+    if s.value in (FK_DONE, FK_FAILED):
+        _ready_events.pop((ctx.value, ticket), None)
     return s.value
 
 

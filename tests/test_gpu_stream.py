@@ -3,11 +3,9 @@ oracle.  The two kernels split the x index over different numbers of waves,
 so they sum in different orders: each must be within the FP32 summation
 bound of the stored-operand oracle, and the stream kernel must be
 deterministic and give every member table bitwise its rows of a group.  The
-persistent kernel is selected with the FKCONV_NO_STREAM environment
-variable.  The cases use the hadronic fit shape (x-grid of 50, groups of at
+persistent kernel is selected with the context option FK_OPT_KERNELS.  The cases use the hadronic fit shape (x-grid of 50, groups of at
 least two k-steps), where the stream kernel applies, over replica counts
 that select every column-tile count."""
-import os
 import sys
 
 import numpy as np
@@ -25,16 +23,18 @@ def say(*a):
     sys.stdout.flush()
 
 
+def kernels(c, stream):
+    fkconv.fk_set_option(c.ctx, fkconv.FK_OPT_KERNELS,
+                         fkconv.FK_KERNELS_STREAM if stream else fkconv.FK_KERNELS_ITEM)
+
+
 def run(c, h, x, stream):
-    if stream:
-        os.environ.pop("FKCONV_NO_STREAM", None)
-    else:
-        os.environ["FKCONV_NO_STREAM"] = "1"
+    kernels(c, stream)
     try:
         y = fkconv.fk_conv_had(c.ctx, h, x)
         torch.cuda.synchronize()
     finally:
-        os.environ.pop("FKCONV_NO_STREAM", None)
+        kernels(c, True)
     return y
 
 
@@ -88,15 +88,12 @@ def test_dis_stream_against_partial_sum_kernel_and_oracle(fmt, R):
         x = torch.from_numpy(pdf.astype(np.float32)).cuda()
 
         def dis(h, stream):
-            if stream:
-                os.environ.pop("FKCONV_NO_STREAM", None)
-            else:
-                os.environ["FKCONV_NO_STREAM"] = "1"
+            kernels(c, stream)
             try:
                 y = fkconv.fk_conv_dis(c.ctx, h, x)
                 torch.cuda.synchronize()
             finally:
-                os.environ.pop("FKCONV_NO_STREAM", None)
+                kernels(c, True)
             return y
 
         ys = dis(g, True)
@@ -132,10 +129,7 @@ def test_timing_kinds_name_the_kernel_that_ran():
         x = torch.from_numpy(w.pdf(R).astype(np.float32)).cuda()
         xd = torch.from_numpy(wd.pdf(R).astype(np.float32)).cuda()
         for stream in (True, False):
-            if stream:
-                os.environ.pop("FKCONV_NO_STREAM", None)
-            else:
-                os.environ["FKCONV_NO_STREAM"] = "1"
+            kernels(c, stream)
             try:
                 fkconv.fk_timing_read(c.ctx)
                 fkconv.fk_timing_enable(c.ctx, True)
@@ -145,7 +139,7 @@ def test_timing_kinds_name_the_kernel_that_ran():
                 fkconv.fk_timing_enable(c.ctx, False)
                 kt = fkconv.fk_timing_read(c.ctx)
             finally:
-                os.environ.pop("FKCONV_NO_STREAM", None)
+                kernels(c, True)
             say(f"stream={stream}: {({k: v[1] for k, v in kt.items() if v[1]})}")
             assert kt["stage"][1] == 2
             if stream:
@@ -161,15 +155,12 @@ def test_timing_kinds_name_the_kernel_that_ran():
 
 
 def run_adj(c, h, x, gbar, stream):
-    if stream:
-        os.environ.pop("FKCONV_NO_STREAM", None)
-    else:
-        os.environ["FKCONV_NO_STREAM"] = "1"
+    kernels(c, stream)
     try:
         g = fkconv.fk_conv_backward(c.ctx, h, x, gbar)
         torch.cuda.synchronize()
     finally:
-        os.environ.pop("FKCONV_NO_STREAM", None)
+        kernels(c, True)
     return g
 
 
