@@ -154,6 +154,21 @@ fk_status fk_table_info(fk_ctx *ctx, fk_table table, int32_t *kind, int32_t *nda
 fk_status fk_conv_dis(fk_ctx *ctx, fk_table table, const double *pdf_xgrid,
                       const float *pdf, int32_t nrep, float *out, void *stream);
 
+/* fk_conv_dis for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same kernels and the same results, bitwise, but the staged PDF operand
+ * lives in a static device array of 4 MiB per GPU (held until the process
+ * ends) instead of the table's scratch, and the call allocates nothing.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (on different streams, or from different contexts) race and must be
+ * ordered by the caller.  FK_E_TOO_LARGE when the table's staged operand
+ * exceeds 4 MiB (it takes about 120 KiB per distinct flavour pattern of 9
+ * flavours on 50 x-points in BF16, 240 KiB in FP32),
+ * FK_E_STATE when the table does not use the streaming DIS kernel; other
+ * arguments and errors as fk_conv_dis. */
+fk_status fk_conv_dis_static(fk_ctx *ctx, fk_table table, const double *pdf_xgrid,
+                             const float *pdf, int32_t nrep, float *out, void *stream);
+
 /* Hadronic observables sigma [ndata][nrep], Eq. (1), of a hadronic
  * table/group.  Same arguments as fk_conv_dis. */
 fk_status fk_conv_had(fk_ctx *ctx, fk_table table, const double *pdf_xgrid,

@@ -22,6 +22,7 @@
 // All partial sums are written to slots and reduced in a fixed order, so
 // results are bitwise reproducible and independent of batch composition.
 #include <algorithm>
+#include <mutex>
 
 #include "fk_internal.h"
 
@@ -1426,6 +1427,36 @@ hipError_t launch_col_err(const float *y, const float *ref, int N, int R, double
   if (N <= 0 || R <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(col_err_kernel, dim3(R), dim3(64), 0, s, y, ref, N, R, out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free entry point (fk_conv_dis_static): a
+// file-scope device array, one copy per GPU, resolved to its device address
+// once per device by static_scratch_resolve.  Host code uses only the
+// resolved address: the array's name is a host-side stand-in.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_resolve(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[device] = p;
+  return hipSuccess;
+}
+
+void *static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
 }
 
 }  // namespace fk

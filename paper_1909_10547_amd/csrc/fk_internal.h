@@ -203,6 +203,15 @@ hipError_t launch_adj_reduce(const ConvLaunch &L, int nrows_out, const int32_t *
 hipError_t launch_col_err(const float *y, const float *ref, int N, int R, double *out,
                           hipStream_t s);
 
+// Static scratch of the allocation-free DIS entry point: kStaticScratchBytes
+// of device memory per GPU (a file-scope __device__ array).  resolve() looks
+// up the array's device address on ``device`` (which must be current) once;
+// static_scratch() returns it (nullptr before resolve).
+constexpr size_t kStaticScratchBytes = 4u << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch_resolve(int device);
+void *static_scratch(int device);
+
 // chi2 (chi2_kernels.hip)
 hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off, double *d_a,
                            double *d_linv, int32_t *d_flag, int maxn, hipStream_t s);

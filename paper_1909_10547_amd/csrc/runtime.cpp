@@ -870,6 +870,10 @@ fk_status fk_create(fk_ctx **out, int32_t device, uint64_t hbm_budget_bytes) {
   size_t fre = 0, tot = 0;
   if ((e = hipMemGetInfo(&fre, &tot)) != hipSuccess)
     return set_err(nullptr, FK_E_HIP, "hipMemGetInfo: %s", hipGetErrorString(e));
+  // the device address of this GPU's static scratch (fk_conv_dis_static)
+  if (device >= kMaxDevices || (e = static_scratch_resolve(device)) != hipSuccess)
+    return set_err(nullptr, FK_E_HIP, "fk_create: static scratch of device %d: %s", device,
+                   device >= kMaxDevices ? "device index too large" : hipGetErrorString(e));
   auto *c = new fk_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fre);
@@ -1169,6 +1173,51 @@ fk_status fk_conv_dis(fk_ctx *ctx, fk_table table, const double *pdf_xgrid, cons
 fk_status fk_conv_had(fk_ctx *ctx, fk_table table, const double *pdf_xgrid, const float *pdf,
                       int32_t nrep, float *out, void *stream) {
   return conv_common(ctx, table, FK_HAD, pdf_xgrid, pdf, nrep, out, stream, "fk_conv_had");
+}
+
+fk_status fk_conv_dis_static(fk_ctx *ctx, fk_table table, const double *pdf_xgrid,
+                             const float *pdf, int32_t nrep, float *out, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  const Plan *p;
+  {
+    Guard g(ctx);
+    p = find_plan(ctx, table);
+    if (!p) return set_err(ctx, FK_E_HANDLE, "fk_conv_dis_static: unknown handle %lld", (long long)table);
+    if (p->kind != FK_DIS)
+      return set_err(ctx, FK_E_ARG, "fk_conv_dis_static: handle %lld holds hadronic tables", (long long)table);
+    if (!pdf || !out) return set_err(ctx, FK_E_ARG, "fk_conv_dis_static: NULL pdf or out");
+    if (nrep < 1) return set_err(ctx, FK_E_ARG, "fk_conv_dis_static: nrep must be >= 1 (got %d)", nrep);
+    if (pdf_xgrid) {
+      const Table *t = find_table(ctx, p->tables[0]);
+      for (int k = 0; t && k < p->X; ++k)
+        if (!(std::fabs(pdf_xgrid[k] - t->xgrid[k]) <= 1e-12 * std::fabs(t->xgrid[k])))
+          return set_err(ctx, FK_E_GRID, "fk_conv_dis_static: PDF x-grid differs from the table's at index %d", k);
+    }
+    if (!p->dis_chunk)
+      return set_err(ctx, FK_E_STATE, "fk_conv_dis_static: handle %lld does not use the streaming DIS "
+                     "kernel (its B operand does not fit the kernel's LDS)", (long long)table);
+    if (p->bop_units * 16 > kStaticScratchBytes)
+      return set_err(ctx, FK_E_TOO_LARGE, "fk_conv_dis_static: the staged PDF operand needs %llu bytes, "
+                     "the static scratch holds %llu", (unsigned long long)(p->bop_units * 16),
+                     (unsigned long long)kStaticScratchBytes);
+  }
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  uint4 *bop = (uint4 *)static_scratch(ctx->device);
+  if (!bop) return set_err(ctx, FK_E_STATE, "fk_conv_dis_static: static scratch not resolved");
+  const hipStream_t s = (hipStream_t)stream;
+  // the DIS stream form of run_forward with the staged operand in the
+  // static scratch: stage, then the stream kernel writes the outputs
+  for (int c0 = 0; c0 < nrep; c0 += p->dis_chunk) {
+    const int ncols = std::min(p->dis_chunk, nrep - c0);
+    ConvLaunch L{p->dtype, pick_nt(ncols), ncols, c0, nrep, s, p->d_zero};
+    hipError_t e = launch_stage_b(L, p->d_gd, p->d_rowtab, p->ngd_fwd, pdf, nullptr, p->d_scale, bop,
+                                  nullptr);
+    if (e == hipSuccess)
+      e = launch_dis_stream(L, p->d_dwgs, p->n_dwgs, p->d_dgroups, bop, p->d_scale, p->dis_ttot_max, out);
+    if (e != hipSuccess)
+      return set_err(ctx, FK_E_HIP, "fk_conv_dis_static: launch failed: %s", hipGetErrorString(e));
+  }
+  return FK_OK;
 }
 
 fk_status fk_conv_backward(fk_ctx *ctx, fk_table table, const float *pdf, const float *grad_out,

@@ -56,6 +56,7 @@ SIGNATURES = {
     "fk_table_info": (_I32, [_P, _I64, _PI32, _PI32, _PI32, _PI32, _PI32, _PU64]),
     "fk_conv_dis": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
     "fk_conv_had": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
+    "fk_conv_dis_static": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
     "fk_conv_backward": (_I32, [_P, _I64, _P, _P, _I32, _P, _I32, _P]),
     "fk_load_covariance": (_I32, [_P, _I32, _P, _P, _PI64]),
     "fk_unload_covariance": (_I32, [_P, _I64]),
@@ -222,6 +223,13 @@ def _conv(fn, ctx, table, pdf, out, pdf_xgrid, stream):
 
 def fk_conv_dis(ctx, table: int, pdf, out=None, pdf_xgrid=None, stream=None):
     return _conv(lib().fk_conv_dis, ctx, table, pdf, out, pdf_xgrid, stream)
+
+
+def fk_conv_dis_static(ctx, table: int, pdf, out=None, pdf_xgrid=None, stream=None):
+    """fk_conv_dis with the staged operand in the library's static scratch
+    (allocates no device memory in the library; calls on one GPU must not
+    overlap)."""
+    return _conv(lib().fk_conv_dis_static, ctx, table, pdf, out, pdf_xgrid, stream)
 
 
 def fk_conv_had(ctx, table: int, pdf, out=None, pdf_xgrid=None, stream=None):
