@@ -34,6 +34,16 @@ What each function follows:
                      luminosity L[(a,b,alpha,beta), r] = f_a(x_alpha) f_b(x_beta)
                      over the active pairs, and the plain product FK[N][K] L[K][R]
                      (a library matmul in FP64).
+* ``mlp_pdf``, ``mlp_pdf_grad``  the PDF as the output of a neural network
+                     sampled on the x-grid (Section 2: the fit parametrises
+                     the PDF with a network trained by gradient descent;
+                     Section 3: the network generates the PDF on the grid
+                     that the convolution consumes), and the gradient of a
+                     linear functional of that PDF with respect to the
+                     network parameters (reverse-mode chain rule, layer by
+                     layer).  The paper gives no architecture; the one here
+                     (inputs x and ln x, two tanh layers, a linear output per
+                     flavour times x^alpha (1-x)^beta) is a reading.
 * ``normwise_rel``, ``error_report``  the error measures every parity test
                      gates on or reports.
 
@@ -364,6 +374,76 @@ def had_grad_quantized(mask, fk, pdf, gbar, fmt: str) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # error measures
 # ---------------------------------------------------------------------------
+
+# ---------------------------------------------------------------------------
+# PDF from a neural network on the x-grid (Sections 2 and 3)
+# ---------------------------------------------------------------------------
+
+def mlp_nparams(nflav: int, h1: int, h2: int) -> int:
+    """Parameters of one replica's network, in the order W1 [h1][2], b1 [h1],
+    W2 [h2][h1], b2 [h2], W3 [nflav][h2], b3 [nflav]."""
+    return h1 * 2 + h1 + h2 * h1 + h2 + nflav * h2 + nflav
+
+
+def mlp_unpack(p, nflav: int, h1: int, h2: int):
+    p = _f64(p)
+    o = 0
+    out = []
+    for shape in ((h1, 2), (h1,), (h2, h1), (h2,), (nflav, h2), (nflav,)):
+        n = int(np.prod(shape))
+        out.append(p[o:o + n].reshape(shape))
+        o += n
+    return out
+
+
+def mlp_preprocessing(xgrid, pre_alpha, pre_beta) -> np.ndarray:
+    """x^alpha_a (1 - x)^beta_a on the grid, [nflav][X]."""
+    x = _f64(xgrid)
+    return x[None, :] ** _f64(pre_alpha)[:, None] * (1.0 - x[None, :]) ** _f64(pre_beta)[:, None]
+
+
+def mlp_pdf(params, xgrid, pre_alpha, pre_beta, h1: int, h2: int) -> np.ndarray:
+    """f[a, alpha, r] = x_alpha^alpha_a (1 - x_alpha)^beta_a NN_r(x_alpha)_a
+    for the network of replica r (params [R][P]): inputs (x, ln x), a tanh
+    layer of h1 units, a tanh layer of h2 units, a linear output per flavour.
+    Returns [nflav][X][R]."""
+    params, x = _f64(params), _f64(xgrid)
+    F = len(pre_alpha)
+    R, X = params.shape[0], len(x)
+    inp = np.stack([x, np.log(x)], axis=1)  # [X][2]
+    pre = mlp_preprocessing(x, pre_alpha, pre_beta)
+    f = np.empty((F, X, R))
+    for r in range(R):
+        W1, b1, W2, b2, W3, b3 = mlp_unpack(params[r], F, h1, h2)
+        a1 = np.tanh(inp @ W1.T + b1)  # [X][h1]
+        a2 = np.tanh(a1 @ W2.T + b2)   # [X][h2]
+        out = a2 @ W3.T + b3           # [X][F]
+        f[:, :, r] = pre * out.T
+    return f
+
+
+def mlp_pdf_grad(params, xgrid, pre_alpha, pre_beta, h1: int, h2: int, gpdf) -> np.ndarray:
+    """Gradient with respect to params [R][P] of sum_{a,alpha,r} gpdf[a,alpha,r]
+    f[a,alpha,r] (gpdf: [nflav][X][R], e.g. d chi2 / d f from the adjoint of
+    the convolution).  Reverse mode: output layer, then each tanh layer with
+    the factor 1 - tanh^2."""
+    params, x, gpdf = _f64(params), _f64(xgrid), _f64(gpdf)
+    F = len(pre_alpha)
+    R = params.shape[0]
+    inp = np.stack([x, np.log(x)], axis=1)
+    pre = mlp_preprocessing(x, pre_alpha, pre_beta)
+    g = np.empty_like(params)
+    for r in range(R):
+        W1, b1, W2, b2, W3, b3 = mlp_unpack(params[r], F, h1, h2)
+        a1 = np.tanh(inp @ W1.T + b1)
+        a2 = np.tanh(a1 @ W2.T + b2)
+        dout = (gpdf[:, :, r] * pre).T        # d/d out, [X][F]
+        d2 = (dout @ W3) * (1.0 - a2 ** 2)    # d/d (W2 a1 + b2), [X][h2]
+        d1 = (d2 @ W2) * (1.0 - a1 ** 2)      # d/d (W1 inp + b1), [X][h1]
+        g[r] = np.concatenate([(d1.T @ inp).ravel(), d1.sum(axis=0), (d2.T @ a1).ravel(),
+                               d2.sum(axis=0), (dout.T @ a2).ravel(), dout.sum(axis=0)])
+    return g
+
 
 def normwise_rel(y, yref) -> float:
     """max over replica columns (the last axis) of ||y - y*||_2 / ||y*||_2;

@@ -20,7 +20,8 @@ import pytest
 ROOT = os.path.dirname(os.path.abspath(os.path.dirname(__file__)))
 SRC = open(os.path.join(ROOT, "oracle", "fkoracle.c")).read()
 PYSRC = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
-PIN_TESTS = ["test_oracle_golden.py", "test_oracle_pins.py", "test_oracle_measures.py"]
+PIN_TESTS = ["test_oracle_golden.py", "test_oracle_pins.py", "test_oracle_measures.py",
+             "test_oracle_mlp.py"]
 
 MUTANTS = {
     "dis_flavour_map": ("pdf[IDX3(flav[c], al, r, X, R)]", "pdf[IDX3(c, al, r, X, R)]"),
@@ -53,6 +54,13 @@ PY_MUTANTS = {
     "bf16_one_bit_short": ('"bf16": (7, -126', '"bf16": (6, -126'),
     "luminosity_a_b_swap": ("L[c] = pdf[a[c]][:, None, :] * pdf[b[c]][None, :, :]",
                             "L[c] = pdf[b[c]][:, None, :] * pdf[a[c]][None, :, :]"),
+    "mlp_no_tanh_derivative": ("d2 = (dout @ W3) * (1.0 - a2 ** 2)", "d2 = (dout @ W3)"),
+    "mlp_first_layer_derivative": ("d1 = (d2 @ W2) * (1.0 - a1 ** 2)", "d1 = (d2 @ W2) * (1.0 - a1)"),
+    "mlp_grad_no_preprocessing": ("dout = (gpdf[:, :, r] * pre).T", "dout = gpdf[:, :, r].T"),
+    "mlp_grad_bias_dropped": ("d2.sum(axis=0), (dout.T @ a2).ravel()", "0 * d2.sum(axis=0), (dout.T @ a2).ravel()"),
+    "mlp_preprocessing_beta_sign": ("(1.0 - x[None, :]) ** _f64(pre_beta)[:, None]",
+                                    "(1.0 + x[None, :]) ** _f64(pre_beta)[:, None]"),
+    "mlp_second_layer_no_tanh": ("a2 = np.tanh(a1 @ W2.T + b2)   # [X][h2]", "a2 = a1 @ W2.T + b2   # [X][h2]"),
 }
 
 
