@@ -141,6 +141,7 @@ def main() -> int:
                     help="skip the large DIS set used for the HBM-bandwidth rows")
     ap.add_argument("--dis-hbm-gib", type=float, default=2.0,
                     help="FP32 table size of the large DIS set")
+    ap.add_argument("--no-table3", action="store_true", help="skip the Table 3 shape rows")
     ap.add_argument("--profile-bf16", action="store_true",
                     help="only load the BF16 tables and run the BF16 step (for profiler runs)")
     ap.add_argument("--profile-adj", action="store_true",
@@ -399,6 +400,9 @@ def main() -> int:
         log("extra rows: DIS, adjoints, chi2, fit step")
         result.setdefault("rows", {}).update(extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv,
                                                     synth))
+    if not args.no_table3:
+        log("Table 3 shapes (flattened form)")
+        result.setdefault("rows", {})["table3"] = table3(c, args, torch, fkconv, synth)
     if not args.no_serve:
         log("serving")
         result.setdefault("rows", {})["serving"] = serving(c, w, tabs, args, torch, fkconv, synth)
@@ -538,6 +542,114 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
     for h in hb + hf:
         fkconv.fk_unload_table(c.ctx, h)
     return res
+
+
+# Table 3 of the paper: (K, R) of the PDF matrix, (N, K) of the FK table, and
+# the printed times in seconds (TensorFlow CPU, AVX, TensorFlow GPU, OpenCL;
+# None where the table prints "~1"), which include the transfer to the GPU.
+TABLE3 = [
+    (35721, 1, 8, (1.10e-2, 1.57e-4, 4.14e-1, None)),
+    (10 ** 6, 1, 8, (4.70e-2, 5.00e-3, 4.49e-1, None)),
+    (10 ** 7, 1, 8, (3.20e-1, 5.70e-2, 7.90e-1, 1.38)),
+    (10 ** 8, 1, 8, (2.90, 5.70e-1, 4.21, 6.31)),
+    (35721, 100, 8, (6.90e-2, 1.60e-2, 4.31e-1, None)),
+    (35721, 1000, 8, (1.50e-1, 1.69e-1, 5.63e-1, None)),
+    (35721, 10 ** 4, 8, (1.12, 1.73, 1.92, 1.76)),
+    (35721, 5 * 10 ** 4, 10, (5.33, 8.93, 7.83, 5.80)),
+    (35721, 1, 100, (2.80e-2, 2.43e-3, 4.24e-1, None)),
+    (35721, 1, 1000, (1.30e-1, 2.14e-2, 5.60e-1, None)),
+    (35721, 1, 10 ** 4, (1.14, 2.16e-1, 1.93, 1.76)),
+    (35721, 100, 100, (6.20e-2, 1.86e-1, 4.32e-1, None)),
+    (35721, 1000, 1000, (3.00e-1, 21.61, 7.19e-1, 5.25)),
+    (35721, 2000, 2000, (5.06, 86.13, 1.38, 15.97)),
+]
+
+
+def table3(c, args, torch, fkconv, synth):
+    """Every row of Table 3 in the flattened form the paper times: FK [N][K]
+    against a PDF matrix [K][R].  For K = 35721 the matrix is the luminosity
+    of 49 flavour pairs on 27 grid points, formed on the device from the PDF;
+    the toy rows (K = 1e6 .. 1e8) use a seeded positive matrix.  Times (s):
+    ``resident`` = the kernels alone (luminosity + product) on resident
+    inputs; ``with_h2d`` = the paper's measurement: copy FK and the K x R
+    matrix from pinned host memory, multiply, copy the result back;
+    ``with_h2d_pdf`` (K = 35721) = copy FK and the PDF only and form the
+    luminosity on the device.  Median of 5 after a warm-up."""
+    rows = []
+    mask = synth.table3_mask()
+    s = torch.cuda.current_stream()
+
+    def med(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts))
+
+    for K, R, N, paper in TABLE3:
+        lumi = K == 35721
+        fk_h = torch.from_numpy(synth.table3_fk(N, K)).pin_memory()
+        fk_d = torch.empty_like(fk_h, device="cuda")
+        fk_d.copy_(fk_h)
+        out_d = torch.empty((N, R), dtype=torch.float32, device="cuda")
+        out_h = torch.empty((N, R), dtype=torch.float32).pin_memory()
+        nw = fkconv.fk_flat_conv_workspace(c.ctx, N, K, R)
+        work = torch.empty(max(nw // 4, 1), dtype=torch.float32, device="cuda")
+        L_d = torch.empty((K, R), dtype=torch.float32, device="cuda")
+        if lumi:
+            pdf_h = torch.from_numpy(synth.table3_pdf(R).astype(np.float32)).pin_memory()
+            pdf_d = pdf_h.cuda()
+            fkconv.fk_luminosity(c.ctx, mask, pdf_d, lum=L_d)
+            L_h = torch.empty((K, R), dtype=torch.float32).pin_memory()
+            L_h.copy_(L_d)
+        else:
+            L_h = torch.from_numpy(synth.table3_matrix(K, R)).pin_memory()
+            L_d.copy_(L_h)
+        torch.cuda.synchronize()
+
+        def resident():
+            if lumi:
+                fkconv.fk_luminosity(c.ctx, mask, pdf_d, lum=L_d)
+            fkconv.fk_flat_conv(c.ctx, fk_d, L_d, out=out_d, work=work)
+
+        def with_h2d():
+            fk_d.copy_(fk_h, non_blocking=True)
+            L_d.copy_(L_h, non_blocking=True)
+            fkconv.fk_flat_conv(c.ctx, fk_d, L_d, out=out_d, work=work)
+            out_h.copy_(out_d, non_blocking=True)
+
+        def with_h2d_pdf():
+            fk_d.copy_(fk_h, non_blocking=True)
+            pdf_d.copy_(pdf_h, non_blocking=True)
+            fkconv.fk_luminosity(c.ctx, mask, pdf_d, lum=L_d)
+            fkconv.fk_flat_conv(c.ctx, fk_d, L_d, out=out_d, work=work)
+            out_h.copy_(out_d, non_blocking=True)
+
+        t_res = med(resident)
+        t_h2d = med(with_h2d)
+        row = {"pdf": [K, R], "fk": [N, K], "resident_s": t_res, "with_h2d_s": t_h2d,
+               "kernel": "mfma" if (N > 16 and R > 16) else "stream",
+               "flop": 2.0 * N * K * R, "bytes_resident": 4.0 * (N * K + K * R + N * R),
+               "paper_s": {"tf_cpu": paper[0], "avx": paper[1], "tf_gpu": paper[2], "opencl": paper[3],
+                           "note": "Table 3, including the transfer to the GPU; None = printed as ~1"}}
+        if lumi:
+            row["with_h2d_pdf_s"] = med(with_h2d_pdf)
+        best = min(v for v in paper if v is not None)
+        row["paper_best_over_with_h2d"] = best / t_h2d
+        rows.append(row)
+        log(f"  Table 3 row PDF {K}x{R} FK {N}x{K}: resident {t_res * 1e3:.3f} ms, with H2D "
+            f"{t_h2d * 1e3:.3f} ms (paper best {best:.3g} s)")
+        del fk_h, fk_d, out_d, out_h, work, L_d, L_h
+        if lumi:
+            del pdf_h, pdf_d
+        torch.cuda.empty_cache()
+    return rows
 
 
 def measured_peaks(torch):

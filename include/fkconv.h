@@ -47,6 +47,7 @@ typedef int32_t fk_status;
 typedef int64_t fk_table;   /* a loaded table or a group of tables */
 typedef int64_t fk_cov;     /* a loaded block-diagonal covariance */
 typedef int64_t fk_ticket;  /* a serving request */
+typedef int64_t fk_mlp;     /* a network PDF parametrisation */
 
 enum {
   FK_OK = 0,
@@ -187,6 +188,76 @@ fk_status fk_conv_had(fk_ctx *ctx, fk_table table, const double *pdf_xgrid,
 fk_status fk_conv_backward(fk_ctx *ctx, fk_table table, const float *pdf,
                            const float *grad_out, int32_t nrep, float *grad_pdf,
                            int32_t accumulate, void *stream);
+
+/* ---- the flattened form of Table 3 ----------------------------------------
+ * Table 3 of the paper times the hadronic convolution as a product of an FK
+ * table N x K with a "PDF" matrix K x R, K = 49 flavour combinations x 27^2
+ * grid points: the PDF enters through the luminosity
+ *   L[(c, alpha, beta)][r] = f[a_c][alpha][r] f[b_c][beta][r]
+ * over the active pairs c = (a_c, b_c), and out = FK L.  These calls
+ * compute that form (for comparison with Table 3; the conv calls above
+ * never form L). */
+
+/* Luminosity of the nonzero entries of ``mask`` (host [nflav][nflav],
+ * taken in row-major (a, b) order, at most 1024):
+ *  pdf  device float32 [nflav][nx][nrep]
+ *  lum  device float32 [npairs * nx * nx][nrep], row (c * nx + alpha) * nx + beta. */
+fk_status fk_luminosity(fk_ctx *ctx, int32_t nflav, int32_t nx, const uint8_t *mask,
+                        const float *pdf, int32_t nrep, float *lum, void *stream);
+
+/* Device bytes of the workspace fk_flat_conv needs for this shape (0 when
+ * it needs none). */
+fk_status fk_flat_conv_workspace(fk_ctx *ctx, int64_t n, int64_t k, int64_t r, uint64_t *bytes);
+
+/* out[n][r] = sum_k fk[n][k] lum[k][r]: FP32 inputs, FP32 accumulation in a
+ * fixed order (so results are reproducible), device row-major arrays
+ *  fk [n][k], lum [k][r], out [n][r];
+ * ``work`` (device, ``work_bytes``) holds the partial sums when K is split
+ * over workgroups (fk_flat_conv_workspace).  n <= 1048560, r <= 4194240.  Few rows or
+ * columns (n <= 16 or r <= 16) stream through the vector units (bound by
+ * HBM), larger products run on the FP32 matrix cores. */
+fk_status fk_flat_conv(fk_ctx *ctx, int64_t n, int64_t k, int64_t r, const float *fk,
+                       const float *lum, float *out, void *work, uint64_t work_bytes,
+                       void *stream);
+
+/* ---- network PDF and gradient descent -------------------------------------
+ * The steps either side of the convolution in a fit: Section 2 describes
+ * fits that parametrise the PDF with a neural network trained by gradient
+ * descent, and Section 3 a network that generates the PDF on the x-grid the
+ * FK tables are convolved with.  The paper gives no architecture; this one
+ * is: inputs (x, ln x), a tanh layer of h1 units, a tanh layer of h2 units,
+ * a linear output per flavour, times x^alpha_a (1 - x)^beta_a:
+ *   f_r[a][alpha] = x^alpha_a (1-x)^beta_a (W3 tanh(W2 tanh(W1 in + b1) + b2) + b3)_a
+ * with one network per replica r.  Parameters of replica r are the row
+ * params[r][P], P = 3 h1 + h2 h1 + h2 + nflav h2 + nflav, in the order
+ * W1 [h1][2], b1 [h1], W2 [h2][h1], b2 [h2], W3 [nflav][h2], b3 [nflav]
+ * (row-major).  FP32 arithmetic; one workgroup per replica. */
+
+/* Describe a network on ``xgrid`` (host [nx], values in (0, 1]) with the
+ * preprocessing exponents pre_alpha, pre_beta (host [nflav]); the grid
+ * features are kept on the device.  *nparams = P (may be NULL).
+ * FK_E_SHAPE unless 1 <= nflav, h1, h2 <= 64, nx <= 256 and one replica's
+ * parameters and activations fit 64 KiB of LDS. */
+fk_status fk_mlp_create(fk_ctx *ctx, int32_t nflav, int32_t nx, const double *xgrid, int32_t h1,
+                        int32_t h2, const double *pre_alpha, const double *pre_beta, fk_mlp *out,
+                        int32_t *nparams);
+fk_status fk_mlp_destroy(fk_ctx *ctx, fk_mlp mlp);
+
+/* pdf (device [nflav][nx][nrep]) = the networks of params (device [nrep][P]). */
+fk_status fk_mlp_forward(fk_ctx *ctx, fk_mlp mlp, const float *params, int32_t nrep, float *pdf,
+                         void *stream);
+
+/* grad_params (device [nrep][P]) = gradient of sum_{a,alpha,r}
+ * grad_pdf[a][alpha][r] f_r[a][alpha] with respect to params: the
+ * reverse pass through the network, e.g. after fk_conv_backward turned
+ * d chi2 / d sigma into grad_pdf.  Each parameter's gradient is summed over
+ * the grid points in order (reproducible). */
+fk_status fk_mlp_backward(fk_ctx *ctx, fk_mlp mlp, const float *params, const float *grad_pdf,
+                          int32_t nrep, float *grad_params, void *stream);
+
+/* Gradient-descent step params[i] -= lr * grad[i] for i < n (device arrays). */
+fk_status fk_sgd_update(fk_ctx *ctx, float *params, const float *grad, int64_t n, float lr,
+                        void *stream);
 
 /* ---- chi2 in FP64 ---------------------------------------------------------
  * chi2_r = (sigma_r - D)^T C^{-1} (sigma_r - D) with C block-diagonal (one

@@ -20,7 +20,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libfkconv.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["conv_kernels.hip", "chi2_kernels.hip", "peak_kernels.hip"]
+HIP_SOURCES = ["conv_kernels.hip", "chi2_kernels.hip", "peak_kernels.hip", "flat_kernels.hip", "mlp_kernels.hip"]
 CPP_SOURCES = ["runtime.cpp", "pack.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

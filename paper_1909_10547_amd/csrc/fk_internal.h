@@ -212,6 +212,43 @@ constexpr int kMaxDevices = 64;
 hipError_t static_scratch_resolve(int device);
 void *static_scratch(int device);
 
+// Flattened form of Table 3 (flat_kernels.hip).  Active flavour pairs of
+// the luminosity, a * 64 + b, in row-major (a, b) order.
+constexpr int kFlatMaxPairs = 1024;
+struct FlatPairs {
+  int32_t n;
+  int16_t ab[kFlatMaxPairs];
+};
+// Launch shape of out[N][R] = FK[N][K] L[K][R]: the matrix-core kernel
+// (64 x 64 tiles) or the streaming kernel (nb rows x cw*vec columns), K split
+// into ks chunks of kchunk (partial sums in a workspace when ks > 1).
+struct FlatPlan {
+  bool mfma = false;
+  int nb = 8, cw = 1, vec = 1, ks = 1;
+  int64_t gx = 1, gy = 1, kchunk = 0;
+  uint64_t work_bytes = 0;
+};
+FlatPlan flat_plan(int64_t N, int64_t K, int64_t R, int ncu);
+hipError_t launch_lumi(const FlatPairs &pairs, int nx, int R, const float *pdf, float *lum,
+                       hipStream_t s);
+hipError_t launch_flat(const FlatPlan &p, int64_t N, int64_t K, int64_t R, const float *fk,
+                       const float *lum, float *out, float *work, hipStream_t s);
+
+// Network PDF (mlp_kernels.hip): one network per replica on the x-grid;
+// d_xin = [2][X] (x, ln x), d_pre = [F][X] (x^alpha (1-x)^beta).
+constexpr int kMlpMaxNx = 256;          // grid points (one thread each)
+constexpr size_t kMlpMaxLds = 65536;    // LDS of one replica's workgroup
+struct MlpDev {
+  int F = 0, X = 0, h1 = 0, h2 = 0;
+  const float *d_xin = nullptr, *d_pre = nullptr;
+};
+int mlp_nparams(int F, int h1, int h2);
+size_t mlp_lds_bytes(int F, int X, int h1, int h2, bool backward);
+hipError_t launch_mlp_forward(const MlpDev &m, const float *params, int R, float *pdf, hipStream_t s);
+hipError_t launch_mlp_backward(const MlpDev &m, const float *params, const float *gpdf, int R,
+                               float *gparams, hipStream_t s);
+hipError_t launch_sgd(float *params, const float *grad, int64_t n, float lr, hipStream_t s);
+
 // chi2 (chi2_kernels.hip)
 hipError_t launch_cholesky(int nblocks, const int32_t *d_n, const int64_t *d_off, double *d_a,
                            double *d_linv, int32_t *d_flag, int maxn, hipStream_t s);

@@ -890,6 +890,7 @@ fk_status fk_destroy(fk_ctx *ctx) {
   (void)hipDeviceSynchronize();
   for (auto &kv : ctx->plans) dev_free_all(ctx, kv.second->allocs);
   for (auto &kv : ctx->covs) dev_free_all(ctx, kv.second->allocs);
+  for (auto &kv : ctx->mlps) dev_free_all(ctx, kv.second->allocs);
   for (auto &kv : ctx->tables) dev_free_all(ctx, kv.second->allocs);
   delete ctx;
   return FK_OK;
@@ -1237,6 +1238,167 @@ fk_status fk_conv_backward(fk_ctx *ctx, fk_table table, const float *pdf, const 
                               &ctx->timing, ctx->kernels.load());
   if (e != hipSuccess)
     return set_err(ctx, FK_E_HIP, "fk_conv_backward: launch failed: %s", hipGetErrorString(e));
+  return FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// flattened form of Table 3
+// ---------------------------------------------------------------------------
+static int device_cus(fk_ctx *ctx) {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || ncu < 1)
+    ncu = 256;
+  return ncu;
+}
+
+fk_status fk_luminosity(fk_ctx *ctx, int32_t nflav, int32_t nx, const uint8_t *mask,
+                        const float *pdf, int32_t nrep, float *lum, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  if (!mask || !pdf || !lum) return set_err(ctx, FK_E_ARG, "fk_luminosity: NULL pointer argument");
+  if (nflav < 1 || nflav > 64 || nx < 1 || nrep < 1)
+    return set_err(ctx, FK_E_SHAPE, "fk_luminosity: need 1 <= nflav <= 64, nx >= 1, nrep >= 1");
+  FlatPairs pairs;
+  pairs.n = 0;
+  for (int a = 0; a < nflav; ++a)
+    for (int b = 0; b < nflav; ++b)
+      if (mask[a * nflav + b]) {
+        if (pairs.n == kFlatMaxPairs)
+          return set_err(ctx, FK_E_SHAPE, "fk_luminosity: more than %d active pairs", kFlatMaxPairs);
+        pairs.ab[pairs.n++] = (int16_t)(a * 64 + b);
+      }
+  if (pairs.n == 0) return set_err(ctx, FK_E_SHAPE, "fk_luminosity: mask has no active pair");
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const hipError_t e = launch_lumi(pairs, nx, nrep, pdf, lum, (hipStream_t)stream);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_luminosity: launch failed: %s", hipGetErrorString(e));
+  return FK_OK;
+}
+
+fk_status fk_flat_conv_workspace(fk_ctx *ctx, int64_t n, int64_t k, int64_t r, uint64_t *bytes) {
+  if (!ctx) return FK_E_ARG;
+  if (!bytes || n < 1 || k < 1 || r < 1)
+    return set_err(ctx, FK_E_ARG, "fk_flat_conv_workspace: need bytes and n, k, r >= 1");
+  *bytes = flat_plan(n, k, r, device_cus(ctx)).work_bytes;
+  return FK_OK;
+}
+
+fk_status fk_flat_conv(fk_ctx *ctx, int64_t n, int64_t k, int64_t r, const float *fk, const float *lum,
+                       float *out, void *work, uint64_t work_bytes, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  if (!fk || !lum || !out || n < 1 || k < 1 || r < 1)
+    return set_err(ctx, FK_E_ARG, "fk_flat_conv: need fk, lum, out and n, k, r >= 1");
+  if (n > 65535LL * 16 || r > 65535LL * 64)
+    return set_err(ctx, FK_E_SHAPE, "fk_flat_conv: need n <= %lld and r <= %lld", 65535LL * 16,
+                   65535LL * 64);
+  const FlatPlan p = flat_plan(n, k, r, device_cus(ctx));
+  if (p.work_bytes > work_bytes || (p.work_bytes && !work))
+    return set_err(ctx, FK_E_ARG, "fk_flat_conv: the workspace needs %llu bytes (got %llu)",
+                   (unsigned long long)p.work_bytes, (unsigned long long)work_bytes);
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const hipError_t e = launch_flat(p, n, k, r, fk, lum, out, (float *)work, (hipStream_t)stream);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_flat_conv: launch failed: %s", hipGetErrorString(e));
+  return FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// network PDF and gradient descent (the steps either side of the convolution)
+// ---------------------------------------------------------------------------
+fk_status fk_mlp_create(fk_ctx *ctx, int32_t nflav, int32_t nx, const double *xgrid, int32_t h1,
+                        int32_t h2, const double *pre_alpha, const double *pre_beta, fk_mlp *out,
+                        int32_t *nparams) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  if (!xgrid || !pre_alpha || !pre_beta || !out)
+    return set_err(ctx, FK_E_ARG, "fk_mlp_create: NULL pointer argument");
+  *out = 0;
+  if (nflav < 1 || nflav > 64 || nx < 1 || nx > kMlpMaxNx || h1 < 1 || h1 > 64 || h2 < 1 || h2 > 64)
+    return set_err(ctx, FK_E_SHAPE, "fk_mlp_create: need 1 <= nflav, h1, h2 <= 64 and 1 <= nx <= %d",
+                   kMlpMaxNx);
+  if (mlp_lds_bytes(nflav, nx, h1, h2, true) > kMlpMaxLds)
+    return set_err(ctx, FK_E_SHAPE, "fk_mlp_create: a replica's parameters and activations need %zu "
+                   "bytes of LDS (at most %zu)", mlp_lds_bytes(nflav, nx, h1, h2, true), kMlpMaxLds);
+  for (int i = 0; i < nx; ++i)
+    if (!(xgrid[i] > 0.0 && xgrid[i] <= 1.0))
+      return set_err(ctx, FK_E_GRID, "fk_mlp_create: x-grid values must lie in (0, 1]");
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  std::vector<float> h((size_t)(2 + nflav) * nx);
+  for (int i = 0; i < nx; ++i) {
+    h[i] = (float)xgrid[i];
+    h[nx + i] = (float)std::log(xgrid[i]);
+  }
+  for (int a = 0; a < nflav; ++a)
+    for (int i = 0; i < nx; ++i)
+      h[(size_t)(2 + a) * nx + i] =
+          (float)(std::pow(xgrid[i], pre_alpha[a]) * std::pow(1.0 - xgrid[i], pre_beta[a]));
+  auto m = std::make_unique<Mlp>();
+  void *d = nullptr;
+  fk_status st = dev_alloc(ctx, h.size() * sizeof(float), &d, &m->allocs);
+  if (st) return st;
+  hipError_t e = hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free_all(ctx, m->allocs);
+    return set_err(ctx, FK_E_HIP, "fk_mlp_create: copy to device: %s", hipGetErrorString(e));
+  }
+  m->dev = MlpDev{nflav, nx, h1, h2, (const float *)d, (const float *)d + 2 * nx};
+  const int64_t id = ctx->next_id++;
+  ctx->mlps[id] = std::move(m);
+  *out = id;
+  if (nparams) *nparams = mlp_nparams(nflav, h1, h2);
+  return FK_OK;
+}
+
+fk_status fk_mlp_destroy(fk_ctx *ctx, fk_mlp mlp) {
+  if (!ctx) return FK_E_ARG;
+  Guard g(ctx);
+  auto it = ctx->mlps.find(mlp);
+  if (it == ctx->mlps.end()) return set_err(ctx, FK_E_HANDLE, "fk_mlp_destroy: unknown handle %lld", (long long)mlp);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  dev_free_all(ctx, it->second->allocs);
+  ctx->mlps.erase(it);
+  return FK_OK;
+}
+
+static fk_status find_mlp(fk_ctx *ctx, fk_mlp mlp, MlpDev *out, const char *name) {
+  Guard g(ctx);
+  auto it = ctx->mlps.find(mlp);
+  if (it == ctx->mlps.end()) return set_err(ctx, FK_E_HANDLE, "%s: unknown network handle %lld", name, (long long)mlp);
+  *out = it->second->dev;
+  return FK_OK;
+}
+
+fk_status fk_mlp_forward(fk_ctx *ctx, fk_mlp mlp, const float *params, int32_t nrep, float *pdf,
+                         void *stream) {
+  if (!ctx) return FK_E_ARG;
+  if (!params || !pdf || nrep < 1) return set_err(ctx, FK_E_ARG, "fk_mlp_forward: need params, pdf, nrep >= 1");
+  MlpDev m;
+  fk_status st = find_mlp(ctx, mlp, &m, "fk_mlp_forward");
+  if (st) return st;
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const hipError_t e = launch_mlp_forward(m, params, nrep, pdf, (hipStream_t)stream);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_mlp_forward: launch failed: %s", hipGetErrorString(e));
+  return FK_OK;
+}
+
+fk_status fk_mlp_backward(fk_ctx *ctx, fk_mlp mlp, const float *params, const float *grad_pdf,
+                          int32_t nrep, float *grad_params, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  if (!params || !grad_pdf || !grad_params || nrep < 1)
+    return set_err(ctx, FK_E_ARG, "fk_mlp_backward: need params, grad_pdf, grad_params, nrep >= 1");
+  MlpDev m;
+  fk_status st = find_mlp(ctx, mlp, &m, "fk_mlp_backward");
+  if (st) return st;
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const hipError_t e = launch_mlp_backward(m, params, grad_pdf, nrep, grad_params, (hipStream_t)stream);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_mlp_backward: launch failed: %s", hipGetErrorString(e));
+  return FK_OK;
+}
+
+fk_status fk_sgd_update(fk_ctx *ctx, float *params, const float *grad, int64_t n, float lr, void *stream) {
+  if (!ctx) return FK_E_ARG;
+  if (!params || !grad || n < 1) return set_err(ctx, FK_E_ARG, "fk_sgd_update: need params, grad, n >= 1");
+  FK_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const hipError_t e = launch_sgd(params, grad, n, lr, (hipStream_t)stream);
+  if (e != hipSuccess) return set_err(ctx, FK_E_HIP, "fk_sgd_update: launch failed: %s", hipGetErrorString(e));
   return FK_OK;
 }
 

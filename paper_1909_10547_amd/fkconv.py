@@ -58,6 +58,14 @@ SIGNATURES = {
     "fk_conv_had": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
     "fk_conv_dis_static": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
     "fk_conv_backward": (_I32, [_P, _I64, _P, _P, _I32, _P, _I32, _P]),
+    "fk_luminosity": (_I32, [_P, _I32, _I32, _P, _P, _I32, _P, _P]),
+    "fk_flat_conv_workspace": (_I32, [_P, _I64, _I64, _I64, _PU64]),
+    "fk_flat_conv": (_I32, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _U64, _P]),
+    "fk_mlp_create": (_I32, [_P, _I32, _I32, _P, _I32, _I32, _P, _P, _PI64, _PI32]),
+    "fk_mlp_destroy": (_I32, [_P, _I64]),
+    "fk_mlp_forward": (_I32, [_P, _I64, _P, _I32, _P, _P]),
+    "fk_mlp_backward": (_I32, [_P, _I64, _P, _P, _I32, _P, _P]),
+    "fk_sgd_update": (_I32, [_P, _P, _P, _I64, ctypes.c_float, _P]),
     "fk_load_covariance": (_I32, [_P, _I32, _P, _P, _PI64]),
     "fk_unload_covariance": (_I32, [_P, _I64]),
     "fk_chi2": (_I32, [_P, _I64, _P, _P, _I32, _P, _P, _P]),
@@ -257,6 +265,105 @@ def fk_conv_backward(ctx, table: int, pdf, grad_out, grad_pdf=None, accumulate=F
                                        _dptr(grad_pdf, "f32", "grad_pdf"), 1 if accumulate else 0,
                                        _stream(stream)))
     return grad_pdf
+
+
+# ---------------------------------------------------------------------------
+# flattened form of Table 3
+# ---------------------------------------------------------------------------
+
+def fk_luminosity(ctx, mask, pdf, lum=None, stream=None):
+    """L[(c, alpha, beta)][r] = f[a_c][alpha][r] f[b_c][beta][r] over the
+    active pairs of ``mask`` (host [nflav][nflav]); pdf [nflav][nx][R]."""
+    import torch
+    mk = np.ascontiguousarray(mask, dtype=np.uint8)
+    F, X, R = pdf.shape
+    if mk.shape != (F, F):
+        raise ValueError(f"mask must be [{F}][{F}]")
+    K = int(mk.astype(bool).sum()) * X * X
+    if lum is None:
+        lum = torch.empty((K, R), dtype=torch.float32, device=pdf.device)
+    if tuple(lum.shape) != (K, R):
+        raise ValueError(f"lum must be [{K}][{R}]")
+    _check(ctx, lib().fk_luminosity(ctx, F, X, _hptr(mk), _dptr(pdf, "f32", "pdf"), R,
+                                    _dptr(lum, "f32", "lum"), _stream(stream)))
+    return lum
+
+
+def fk_flat_conv_workspace(ctx, n: int, k: int, r: int) -> int:
+    b = ctypes.c_uint64()
+    _check(ctx, lib().fk_flat_conv_workspace(ctx, n, k, r, ctypes.byref(b)))
+    return b.value
+
+
+def fk_flat_conv(ctx, fk, lum, out=None, work=None, stream=None):
+    """out[N][R] = fk[N][K] lum[K][R] (FP32); allocates the workspace when
+    none is given."""
+    import torch
+    N, K = fk.shape
+    K2, R = lum.shape
+    if K2 != K:
+        raise ValueError("fk and lum disagree on K")
+    if out is None:
+        out = torch.empty((N, R), dtype=torch.float32, device=fk.device)
+    need = fk_flat_conv_workspace(ctx, N, K, R)
+    if work is None and need:
+        work = torch.empty(need // 4, dtype=torch.float32, device=fk.device)
+    wp = _dptr(work, "f32", "work") if work is not None else None
+    wb = work.numel() * 4 if work is not None else 0
+    _check(ctx, lib().fk_flat_conv(ctx, N, K, R, _dptr(fk, "f32", "fk"), _dptr(lum, "f32", "lum"),
+                                   _dptr(out, "f32", "out"), wp, wb, _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# network PDF and gradient descent
+# ---------------------------------------------------------------------------
+
+def fk_mlp_create(ctx, xgrid, h1: int, h2: int, pre_alpha, pre_beta):
+    """(handle, nparams) of a network PDF on ``xgrid``; nflav = len(pre_alpha)."""
+    xg = np.ascontiguousarray(xgrid, dtype=np.float64)
+    pa = np.ascontiguousarray(pre_alpha, dtype=np.float64)
+    pb = np.ascontiguousarray(pre_beta, dtype=np.float64)
+    if pa.shape != pb.shape or pa.ndim != 1:
+        raise ValueError("pre_alpha and pre_beta must be [nflav]")
+    h, n = ctypes.c_int64(), ctypes.c_int32()
+    _check(ctx, lib().fk_mlp_create(ctx, len(pa), len(xg), _hptr(xg), h1, h2, _hptr(pa), _hptr(pb),
+                                    ctypes.byref(h), ctypes.byref(n)))
+    return h.value, n.value
+
+
+def fk_mlp_destroy(ctx, mlp: int):
+    _check(ctx, lib().fk_mlp_destroy(ctx, mlp))
+
+
+def fk_mlp_forward(ctx, mlp: int, params, nflav: int, nx: int, pdf=None, stream=None):
+    import torch
+    R = params.shape[0]
+    if pdf is None:
+        pdf = torch.empty((nflav, nx, R), dtype=torch.float32, device=params.device)
+    _check(ctx, lib().fk_mlp_forward(ctx, mlp, _dptr(params, "f32", "params"), R,
+                                     _dptr(pdf, "f32", "pdf"), _stream(stream)))
+    return pdf
+
+
+def fk_mlp_backward(ctx, mlp: int, params, grad_pdf, grad_params=None, stream=None):
+    import torch
+    R = params.shape[0]
+    if grad_pdf.shape[2] != R:
+        raise ValueError("grad_pdf must be [nflav][nx][R] with the params' R")
+    if grad_params is None:
+        grad_params = torch.empty_like(params)
+    _check(ctx, lib().fk_mlp_backward(ctx, mlp, _dptr(params, "f32", "params"),
+                                      _dptr(grad_pdf, "f32", "grad_pdf"), R,
+                                      _dptr(grad_params, "f32", "grad_params"), _stream(stream)))
+    return grad_params
+
+
+def fk_sgd_update(ctx, params, grad, lr: float, stream=None):
+    if params.shape != grad.shape:
+        raise ValueError("params and grad differ in shape")
+    _check(ctx, lib().fk_sgd_update(ctx, _dptr(params, "f32", "params"), _dptr(grad, "f32", "grad"),
+                                    params.numel(), lr, _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

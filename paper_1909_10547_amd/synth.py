@@ -400,6 +400,74 @@ def serving_workload(scale: float = 1.0, big_n: int = 2000) -> ServingWorkload:
 
 
 # ---------------------------------------------------------------------------
+# network PDF parametrisation: initial parameters and preprocessing
+# ---------------------------------------------------------------------------
+
+MLP_H1, MLP_H2 = 25, 20   # hidden layer widths of the fit-step network
+_S_MLP = 600
+
+
+def mlp_preprocessing_exponents(nflav: int = NFLAV, seed: int = 3):
+    """(alpha [F], beta [F]) of x^alpha (1-x)^beta, drawn like the PDF
+    exponents of the workloads (alpha ~ U(-0.3, 0.8), beta ~ U(1, 5))."""
+    rng = rng_for(seed, _S_MLP)
+    return rng.uniform(-0.3, 0.8, size=nflav), rng.uniform(1.0, 5.0, size=nflav)
+
+
+def mlp_init(nrep: int, nflav: int = NFLAV, h1: int = MLP_H1, h2: int = MLP_H2,
+             seed: int = 3) -> np.ndarray:
+    """Initial parameters of ``nrep`` independent networks, float32
+    [nrep][P] in the layout W1 [h1][2], b1, W2 [h2][h1], b2, W3 [F][h2], b3:
+    weights N(0, 1/fan_in), biases N(0, 0.1); the output bias is centred on 1
+    so that the initial PDF is close to its preprocessing factor."""
+    rng = rng_for(seed, _S_MLP + 1)
+    parts = []
+    for r in range(nrep):
+        parts.append(np.concatenate([
+            rng.normal(scale=1.0 / np.sqrt(2.0), size=h1 * 2), rng.normal(scale=0.1, size=h1),
+            rng.normal(scale=1.0 / np.sqrt(h1), size=h2 * h1), rng.normal(scale=0.1, size=h2),
+            rng.normal(scale=1.0 / np.sqrt(h2), size=nflav * h2), 1.0 + rng.normal(scale=0.1, size=nflav)]))
+    return np.asarray(parts, dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
+# the shapes of Table 3 (flattened form: FK N x K against a PDF matrix K x R)
+# ---------------------------------------------------------------------------
+
+TABLE3_NX = 27       # grid of the base table
+TABLE3_NFLAV7 = 7    # 7 x 7 = 49 flavour combinations, K = 49 * 27^2 = 35721
+_S_TABLE3 = 500
+
+
+def table3_mask(seed: int = 5) -> np.ndarray:
+    """[14][14] mask with the 49 pairs of 7 seeded flavours (a, b both in the
+    set): the base table's 49 flavour combinations."""
+    fl = np.sort(rng_for(seed, _S_TABLE3).choice(NFLAV, size=TABLE3_NFLAV7, replace=False))
+    mask = np.zeros((NFLAV, NFLAV), dtype=np.uint8)
+    mask[np.ix_(fl, fl)] = 1
+    return mask
+
+
+def table3_pdf(nrep: int, seed: int = 5) -> np.ndarray:
+    """PDF replicas on the 27-point grid geomspace(1e-7, 1), float64 [14][27][R]."""
+    prm = draw_pdf_params(rng_for(seed, _S_TABLE3 + 1))
+    return sample_pdf(prm, xgrid_geom(1e-7, 1.0, TABLE3_NX), nrep, 0.05 if nrep > 1 else 0.0,
+                      rng_for(seed, _S_TABLE3 + 2))
+
+
+def table3_fk(n: int, k: int, seed: int = 5) -> np.ndarray:
+    """A flattened FK table [n][k] of N(0,1) entries, float32 (the toy tables
+    of Table 3 carry no structure beyond their size)."""
+    return rng_for(seed, _S_TABLE3 + 3 + n).standard_normal((n, k), dtype=np.float32)
+
+
+def table3_matrix(k: int, r: int, seed: int = 5) -> np.ndarray:
+    """A toy PDF matrix [k][r] for the rows of Table 3 whose K is not a
+    luminosity (K = 1e6 .. 1e8): positive, like PDF products, float32."""
+    return rng_for(seed, _S_TABLE3 + 4 + r).uniform(0.0, 2.0, size=(k, r)).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
 # small helpers for tests
 # ---------------------------------------------------------------------------
 
