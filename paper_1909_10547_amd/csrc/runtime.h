@@ -125,6 +125,11 @@ struct Cov {
   uint64_t bytes = 0;
 };
 
+struct Mlp {
+  MlpDev dev;
+  std::vector<std::pair<void *, size_t>> allocs;
+};
+
 }  // namespace fk
 
 struct fk_ctx {
@@ -137,6 +142,7 @@ struct fk_ctx {
   std::map<int64_t, std::unique_ptr<fk::Table>> tables;
   std::map<int64_t, std::unique_ptr<fk::Plan>> plans;  // table handles and group handles
   std::map<int64_t, std::unique_ptr<fk::Cov>> covs;
+  std::map<int64_t, std::unique_ptr<fk::Mlp>> mlps;
   fk_serve *serve = nullptr;
   fk::Timing timing;
   std::atomic<int> kernels{FK_KERNELS_STREAM};  // fk_set_option(FK_OPT_KERNELS)
