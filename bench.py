@@ -839,6 +839,37 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
     ms, per = time_steps(fit_step, args.steps, args.warmup, torch)
     rows["fit_step_bf16"] = {"ms_per_step": ms, "p50_ms": float(np.median(per)),
                              "note": "DIS + hadronic forward, FP64 chi2 with gradient, both adjoints"}
+    # the whole descent step on the device: network PDF on the x-grid, the
+    # step above, the reverse pass through the network, the update
+    pa, pb = synth.mlp_preprocessing_exponents()
+    m, P = fkconv.fk_mlp_create(c.ctx, w.xgrid, synth.MLP_H1, synth.MLP_H2, pa, pb)
+    params = torch.from_numpy(synth.mlp_init(R)).cuda()
+    gpar = torch.empty_like(params)
+    fnet = torch.empty_like(x)
+
+    lr = [0.0]
+
+    def descent_step():
+        Nd = sum(t.ndata for t in dtabs)
+        fkconv.fk_mlp_forward(c.ctx, m, params, fnet.shape[0], fnet.shape[1], pdf=fnet)
+        fkconv.fk_conv_dis(c.ctx, gd, fnet, out=sig_all[:Nd])
+        fkconv.fk_conv_had(c.ctx, gb, fnet, out=sig_all[Nd:])
+        _, dchi = fkconv.fk_chi2(c.ctx, cv, sig_all, D)
+        fkconv.fk_conv_backward(c.ctx, gd, None, dchi[:Nd].contiguous(), grad_pdf=gpdf)
+        fkconv.fk_conv_backward(c.ctx, gb, fnet, dchi[Nd:].contiguous(), grad_pdf=gpdf, accumulate=True)
+        fkconv.fk_mlp_backward(c.ctx, m, params, gpdf, grad_params=gpar)
+        fkconv.fk_sgd_update(c.ctx, params, gpar, lr[0])
+
+    # a rate whose first step moves no parameter by more than 1e-3
+    descent_step()
+    lr[0] = 1e-3 / float(gpar.abs().max())
+    ms, per = time_steps(descent_step, args.steps, args.warmup, torch)
+    rows["descent_step_bf16"] = {"ms_per_step": ms, "p50_ms": float(np.median(per)), "replicas": R,
+                                 "network": f"(x, ln x) -> {synth.MLP_H1} tanh -> {synth.MLP_H2} tanh -> 14, "
+                                            f"{P} parameters per replica",
+                                 "note": "network PDF, DIS + hadronic forward (BF16 tables), FP64 chi2, both "
+                                         "adjoints, reverse pass through the network, gradient-descent update"}
+    fkconv.fk_mlp_destroy(c.ctx, m)
     fkconv.fk_unload_table(c.ctx, gd)
     for h in hs:
         fkconv.fk_unload_table(c.ctx, h)

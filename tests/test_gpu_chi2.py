@@ -148,3 +148,36 @@ def test_fit_gradient_against_oracle(ctx):
     for hdl in (gd, gh, *hd, *hh):
         fkconv.fk_unload_table(ctx.ctx, hdl)
     fkconv.fk_unload_covariance(ctx.ctx, cv)
+
+
+@pytest.mark.parametrize("cond", [1e4, 1e8, 1e12])
+def test_chi2_ill_conditioned_covariance(ctx, cond):
+    """The per-call products use the triangular inverse of L computed at load
+    time; on covariances with condition numbers up to 1e12 (eigenvalues
+    spread log-uniformly, random eigenvectors) chi2 and its gradient still
+    match the oracle's substitutions to the accuracy FP64 allows for that
+    condition number (relative error <= 1e-15 * cond, at least 1e-11)."""
+    rng = np.random.default_rng(int(np.log10(cond)))
+    sizes = [40, 97]
+    Cs = []
+    for n in sizes:
+        Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        ev = np.geomspace(1.0, 1.0 / cond, n)
+        C = (Q * ev) @ Q.T
+        Cs.append(0.5 * (C + C.T))
+    Ntot, R = sum(sizes), 16
+    sig = f32(rng.normal(size=(Ntot, R)))
+    D = rng.normal(size=Ntot)
+    cv = fkconv.fk_load_covariance(ctx.ctx, Cs)
+    chi, d = fkconv.fk_chi2(ctx.ctx, cv, torch.from_numpy(sig.astype(np.float32)).cuda(),
+                            torch.from_numpy(D).cuda())
+    torch.cuda.synchronize()
+    ref, dref = oracle.chi2([oracle.cholesky(C) for C in Cs], sig, D)
+    e = float(np.max(np.abs(chi.cpu().numpy() - ref) / np.abs(ref)))
+    dgot = d.cpu().double().numpy()
+    # the gradient is returned in FP32: compare to the FP32-rounded reference scale
+    eg = oracle.normwise_rel(dgot, dref)
+    say(f"chi2 cond={cond:.0e}: rel err {e:.2e}, gradient {eg:.2e}")
+    fkconv.fk_unload_covariance(ctx.ctx, cv)
+    assert e <= max(1e-11, 1e-15 * cond)
+    assert eg <= max(1e-6, 1e-15 * cond)
