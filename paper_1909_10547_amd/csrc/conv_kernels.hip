@@ -49,6 +49,12 @@ struct Mma<FK_BF16> {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
+  // c = a * b (the accumulator operand is the constant zero)
+  static __device__ __forceinline__ void first(u32x4 a, u32x4 b, f32x4 &c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b),
+                                                f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  }
 };
 
 template <>
@@ -56,6 +62,13 @@ struct Mma<FK_F32> {
   static constexpr int E = 4;
   static __device__ __forceinline__ void run(u32x4 a, u32x4 b, f32x4 &c) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void first(u32x4 a, u32x4 b, f32x4 &c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x),
+                                             f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
@@ -73,6 +86,10 @@ struct Mma<FK_FP8E4M3> {
     c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ void first(u32x4 a, u32x4 b, f32x4 &c) {
+    c = f32x4{0.f, 0.f, 0.f, 0.f};
+    run(a, b, c);
+  }
 };
 
 // Table pointers come from descriptors in memory, so the compiler cannot
@@ -80,6 +97,11 @@ struct Mma<FK_FP8E4M3> {
 // the LDS wait counter as well: every LDS read of the B operand would then
 // wait for the in-flight HBM prefetch.  The tables live in global memory.
 typedef const __attribute__((address_space(1))) u32x4 *gu32x4_ptr;
+// Buffer descriptors (raw, stride 0): the fourth word of a gfx9-family
+// descriptor for untyped 32-bit accesses, and the load cache policy
+// "non-temporal" (the table streams once).
+constexpr int kBufferRsrcWord3 = 0x00020000;
+constexpr int kLoadNT = 2;
 __device__ __forceinline__ gu32x4_ptr as_global(const void *p) { return (gu32x4_ptr)p; }
 
 // A operand of one tile: T k-steps of the row block stored unit-major
@@ -514,7 +536,6 @@ __global__ void __launch_bounds__(64 * S, 1)
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int r_begin = wg_ptr[blockIdx.x], r_end = wg_ptr[blockIdx.x + 1];
   if (r_begin >= r_end) return;
-  const gu32x4_ptr zpg = as_global(zp);
 
   u32x4 a0[W], a1[W];
   f32x4 acc0[NT], acc1[NT], sacc0[NT], sacc1[NT];
@@ -544,7 +565,13 @@ __global__ void __launch_bounds__(64 * S, 1)
                   w, lane);
   };
 
-  // refill cursor: record rr, job alpha r_al, k-step r_t
+  // refill cursor: record rr, job alpha r_al, k-step r_t.  The two tiles
+  // of the current job are read through buffer descriptors whose size is the
+  // tile, so the hardware returns zeros for units past the row's end (u >=
+  // KE); lanes whose row is absent (row >= nv) get an offset beyond any
+  // tile; past the end of the list the descriptors are empty.  The lane's
+  // offset within a k-step is fixed per record; the k-step adds a uniform
+  // offset.
   int rr = r_begin, r_al = w, r_t = 0;
   bool r_done = false;
   StreamSeg Rq = recs[rr];
@@ -552,18 +579,32 @@ __global__ void __launch_bounds__(64 * S, 1)
   // packer); adjoint copy: each block's tiles follow one another
   auto stride0 = [](const StreamSeg &q) { return (size_t)(ADJ ? q.nv0 : q.nv0 + q.nv1) * q.KE; };
   auto stride1 = [](const StreamSeg &q) { return (size_t)(ADJ ? q.nv1 : q.nv0 + q.nv1) * q.KE; };
-  gu32x4_ptr pa0 = as_global(Rq.a0) + r_al * stride0(Rq);
-  gu32x4_ptr pa1 = as_global(Rq.a1) + r_al * stride1(Rq);
-  // Two loads per call on every path (past the end of the list, of the zero
-  // page); the cursor advance has no loads.
+  constexpr unsigned kNoRow = 0x80000000u;  // beyond every tile (<= 8 KiB)
+  __amdgpu_buffer_rsrc_t rs0, rs1;
+  unsigned vo0 = 0, vo1 = 0, ko0 = 0, ko1 = 0;
+  auto set_tiles = [&]() {
+    const u32x4 *p0 = (const u32x4 *)Rq.a0 + r_al * stride0(Rq);
+    const u32x4 *p1 = Rq.a1 ? (const u32x4 *)Rq.a1 + r_al * stride1(Rq) : zp;
+    rs0 = __builtin_amdgcn_make_buffer_rsrc((void *)p0, (short)0, r_done ? 0 : Rq.KE * Rq.nv0 * 16,
+                                            kBufferRsrcWord3);
+    rs1 = __builtin_amdgcn_make_buffer_rsrc((void *)p1, (short)0, r_done ? 0 : Rq.KE * Rq.nv1 * 16,
+                                            kBufferRsrcWord3);
+    ko0 = ko1 = 0;
+  };
+  auto set_lanes = [&]() {
+    vo0 = c < Rq.nv0 ? (unsigned)(g * Rq.nv0 + c) * 16u : kNoRow;
+    vo1 = c < Rq.nv1 ? (unsigned)(g * Rq.nv1 + c) * 16u : kNoRow;
+  };
+  set_tiles();
+  set_lanes();
+  // Two loads per call on every path (past the end of the list, of empty
+  // descriptors); the cursor advance has no loads.
   auto refill = [&](u32x4 &x0, u32x4 &x1) {
-    const int u = 4 * r_t + g;
-    const bool ok0 = !r_done && c < Rq.nv0 && u < Rq.KE;
-    const bool ok1 = !r_done && c < Rq.nv1 && u < Rq.KE;
-    // offsets inside one tile are small: 32-bit arithmetic
-    x0 = __builtin_nontemporal_load(ok0 ? pa0 + (u * Rq.nv0 + c) : zpg + lane);
-    x1 = __builtin_nontemporal_load(ok1 ? pa1 + (u * Rq.nv1 + c) : zpg + lane);
+    x0 = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs0, vo0 + ko0, 0, kLoadNT));
+    x1 = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs1, vo1 + ko1, 0, kLoadNT));
     if (!r_done) {
+      ko0 += 64u * Rq.nv0;
+      ko1 += 64u * Rq.nv1;
       if (++r_t == Rq.T) {
         r_t = 0;
         r_al += S;
@@ -573,10 +614,10 @@ __global__ void __launch_bounds__(64 * S, 1)
             r_done = true;
           } else {
             Rq = recs[rr];
+            set_lanes();
           }
         }
-        pa0 = as_global(Rq.a0) + r_al * stride0(Rq);
-        pa1 = as_global(Rq.a1) + r_al * stride1(Rq);
+        set_tiles();
       }
     }
   };
@@ -655,10 +696,19 @@ __global__ void __launch_bounds__(64 * S, 1)
 
   auto consume = [&](const u32x4 &x0, const u32x4 &x1) {
     if (done) return;
+    // the first k-step of a job starts the accumulators from zero
+    if (c_t == 0) {
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      Mma<DT>::run(x0, b[j], acc0[j]);
-      Mma<DT>::run(x1, b[j], acc1[j]);
+      for (int j = 0; j < NT; ++j) {
+        Mma<DT>::first(x0, b[j], acc0[j]);
+        Mma<DT>::first(x1, b[j], acc1[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        Mma<DT>::run(x0, b[j], acc0[j]);
+        Mma<DT>::run(x1, b[j], acc1[j]);
+      }
     }
     const bool job_end = ++c_t == Cq.T;
     const bool rec_end = job_end && c_al + S >= nx;
@@ -687,8 +737,6 @@ __global__ void __launch_bounds__(64 * S, 1)
           // branch-free: both rows are updated, one of them by zero
           gr0[j] += g == c_k ? v : 0.f;
           gr1[j] += g == c_k - 4 ? v : 0.f;
-          acc0[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-          acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
       } else {
         const float *fl = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c_al * RP + c;
@@ -700,8 +748,6 @@ __global__ void __launch_bounds__(64 * S, 1)
         for (int j = 0; j < NT; ++j) {
           sacc0[j] += acc0[j] * fv[j];
           sacc1[j] += acc1[j] * fv[j];
-          acc0[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-          acc1[j] = f32x4{0.f, 0.f, 0.f, 0.f};
           __builtin_amdgcn_sched_barrier(0);
         }
       }
