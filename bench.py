@@ -311,6 +311,14 @@ def main() -> int:
             "mfma_counters": mfma_from_counters(),
         },
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt_b.items() if v[1]},
+        # device memory held by the loaded tables (the analogue of the
+        # paper's Table 2): forward copy over unordered pairs + the adjoint's
+        # full rows + per-table plan scratch, per storage format
+        "memory_bytes": {
+            "bf16_tables": sum(fkconv.fk_table_info(c.ctx, h)["device_bytes"] for h in hb),
+            "fp32_tables": sum(fkconv.fk_table_info(c.ctx, h)["device_bytes"] for h in hf),
+            "context_total": fkconv.fk_memory(c.ctx)[0],
+        },
     }
 
     if not args.no_cpu_baseline:

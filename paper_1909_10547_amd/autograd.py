@@ -1,14 +1,36 @@
-"""torch.autograd wrappers: the convolution (forward = fk_conv_dis/had,
-backward = the hand-written adjoint fk_conv_backward) and the FP64 chi2
-(backward = its gradient 2 C^{-1}(sigma - D)), which is what a
-gradient-descent PDF fit differentiates (Section 2: n3fit replaces the
-genetic algorithm with gradient descent; Section 3: the custom operator
-returns the convolution and its gradient)."""
+"""torch.autograd wrappers: the network PDF on the x-grid (forward =
+fk_mlp_forward, backward = the reverse pass fk_mlp_backward), the
+convolution (forward = fk_conv_dis/had, backward = the hand-written adjoint
+fk_conv_backward) and the FP64 chi2 (backward = its gradient
+2 C^{-1}(sigma - D)): the chain a gradient-descent PDF fit differentiates
+(Section 2: the fit trains a network by gradient descent; Section 3: the
+network generates the PDF on the grid, and the custom operator returns the
+convolution and its gradient)."""
 from __future__ import annotations
 
 import torch
 
 from . import fkconv
+
+
+class _Mlp(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, params, fkctx, mlp, nflav, nx):
+        p = params.contiguous()
+        ctx.save_for_backward(p)
+        ctx.fk = (fkctx, mlp)
+        return fkconv.fk_mlp_forward(fkctx, mlp, p, nflav, nx)
+
+    @staticmethod
+    def backward(ctx, gpdf):
+        (p,) = ctx.saved_tensors
+        fkctx, mlp = ctx.fk
+        return fkconv.fk_mlp_backward(fkctx, mlp, p, gpdf.contiguous()), None, None, None, None
+
+
+def mlp_pdf(fkctx, mlp: int, params: torch.Tensor, nflav: int, nx: int) -> torch.Tensor:
+    """Differentiable PDF [nflav][nx][R] of the networks params [R][P]."""
+    return _Mlp.apply(params, fkctx, mlp, nflav, nx)
 
 
 class _Conv(torch.autograd.Function):

@@ -879,7 +879,7 @@ __global__ void __launch_bounds__(64 * S)
   const DisStreamWG wg = wgs[blockIdx.x];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const gu32x4_ptr zpg = as_global(zp);
+  (void)lane;
   // B of every group, then the scales of the range's datapoints; each
   // thread issues up to eight loads before it stores any
   constexpr int NTHR = 64 * S;
@@ -919,56 +919,96 @@ __global__ void __launch_bounds__(64 * S)
   f32x4 acc[NT];
   zero(acc);
 
-  // refill cursor: block rb (relative), group rg, k-step rt of the group
+  // refill cursor: block rb (relative), group rg, k-step rt of the group.
+  // The group's tile of the block is read through a buffer descriptor sized
+  // to the tile (zeros past the row's end); absent rows (the last block of
+  // a table) get an offset beyond the tile, and past the end of the list
+  // the descriptor is empty (see had_stream_kernel).
   int rb = w, rg = wg.g0, rt = 0;
   bool r_done = false;
   DisGroupRef G = groups[rg];
   int rnv = min(16, wg.ndata - 16 * (wg.block0 + rb));
-  gu32x4_ptr pa = as_global(G.base) + (size_t)(wg.block0 + rb) * 16 * G.KE;
+  constexpr unsigned kNoRow = 0x80000000u;
+  __amdgpu_buffer_rsrc_t rs;
+  unsigned vo = 0, ko = 0;
+  auto set_tile = [&]() {
+    const u32x4 *p = (const u32x4 *)G.base + (size_t)(wg.block0 + rb) * 16 * G.KE;
+    rs = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, r_done ? 0 : G.KE * rnv * 16,
+                                           kBufferRsrcWord3);
+    ko = 0;
+  };
+  auto set_lane = [&]() { vo = c < rnv ? (unsigned)(g * rnv + c) * 16u : kNoRow; };
+  set_tile();
+  set_lane();
   auto refill = [&](u32x4 &x) {
-    const int u = 4 * rt + g;
-    const bool ok = !r_done && c < rnv && u < G.KE;
-    x = __builtin_nontemporal_load(ok ? pa + (u * rnv + c) : zpg + lane);
-    if (!r_done && ++rt == G.T) {
-      rt = 0;
-      if (++rg == wg.g1) {
-        rg = wg.g0;
-        rb += S;
-        if (rb >= wg.nblk) r_done = true;
-        else rnv = min(16, wg.ndata - 16 * (wg.block0 + rb));
+    x = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + ko, 0, kLoadNT));
+    if (!r_done) {
+      ko += 64u * rnv;
+      if (++rt == G.T) {
+        rt = 0;
+        if (++rg == wg.g1) {
+          rg = wg.g0;
+          rb += S;
+          if (rb >= wg.nblk) {
+            r_done = true;
+          } else {
+            rnv = min(16, wg.ndata - 16 * (wg.block0 + rb));
+            set_lane();
+          }
+        }
+        G = groups[rg];
+        set_tile();
       }
-      G = groups[rg];
-      pa = as_global(G.base) + (size_t)(wg.block0 + rb) * 16 * G.KE;
     }
   };
-  // consume cursor: block cb, k-step q over all groups of the block
+  // consume cursor: block cb, k-step q over all groups of the block.  The
+  // B fragments of the next k-step are read right after the MFMAs of this
+  // one, so their LDS latency overlaps the refill.
   int cb = w, q = 0;
   bool done = false;
-  auto consume = [&](const u32x4 &x) {
-    if (done) return;
+  u32x4 b[NT];
+  auto read_b = [&]() {
     const u32x4 *bp = lds + (4 * q + g) * RP + c;
-    u32x4 b[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) b[j] = bp[16 * j];
-    __builtin_amdgcn_sched_barrier(0);
+  };
+  read_b();
+  auto consume = [&](const u32x4 &x) {
+    if (done) return;
+    // the first k-step of a block starts the accumulators from zero
+    if (q == 0) {
 #pragma unroll
-    for (int j = 0; j < NT; ++j) Mma<DT>::run(x, b[j], acc[j]);
-    if (++q == wg.ttot) {
-      q = 0;
+      for (int j = 0; j < NT; ++j) Mma<DT>::first(x, b[j], acc[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) Mma<DT>::run(x, b[j], acc[j]);
+    }
+    const bool blk_end = ++q == wg.ttot;
+    if (blk_end) q = 0;
+    if (!blk_end || cb + S < wg.nblk) read_b();
+    __builtin_amdgcn_sched_barrier(0);
+    if (blk_end) {
+      // the block's outputs through a descriptor over its rows: a fixed
+      // number of stores (no branches, so the waits on the ring stay
+      // exact); absent rows and columns past the pass get an offset beyond
+      // it and the hardware drops them
       const int row0 = 16 * cb;  // first row of the block within the range
       const int nv = min(16, wg.ndata - 16 * (wg.block0 + cb));
+      float *ob = out + (size_t)(wg.orow0 + 16 * (wg.block0 + cb)) * R + c0;
+      const __amdgpu_buffer_rsrc_t rso =
+          __builtin_amdgcn_make_buffer_rsrc((void *)ob, (short)0, 16 * R * 4, kBufferRsrcWord3);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = 4 * g + e;
-        if (r < nv) {
-          const float sc = sl[row0 + r];
-          float *o = out + (size_t)(wg.orow0 + 16 * (wg.block0 + cb) + r) * R + c0;
+        const float sc = sl[row0 + min(r, nv - 1)];
 #pragma unroll
-          for (int j = 0; j < NT; ++j)
-            if (16 * j + c < ncols) o[16 * j + c] = sc * acc[j][e];
+        for (int j = 0; j < NT; ++j) {
+          const bool ok = r < nv && 16 * j + c < ncols;
+          const unsigned off = ok ? (unsigned)(r * R + 16 * j + c) * 4u : kNoRow;
+          // the builtin takes the 32 bits as an unsigned integer
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, sc * acc[j][e]), rso, off, 0, 0);
         }
       }
-      zero(acc);
       cb += S;
       if (cb >= wg.nblk) done = true;
     }

@@ -175,3 +175,33 @@ def test_fit_step_full_size():
         eg = oracle.normwise_rel(g.T, g_r.T)
         say(f"  {fmt}: chi2 {ec:.2e}, d chi2 / d params {eg:.2e} (oracle {time.time() - t0:.1f}s)")
         assert ec <= tol and eg <= tol
+
+
+def test_autograd_chain_equals_explicit_calls():
+    """network -> convolutions -> chi2 through torch.autograd gives the
+    parameter gradient of the explicit chain of entry points (to FP32
+    rounding: torch adds the two convolutions' PDF gradients itself)."""
+    from paper_1909_10547_amd import autograd
+    case = fit_case(0.1, 0.05, 4)
+    with fkconv.Context(0) as c:
+        _, g_explicit, _ = gpu_chain(c, case, "f32")
+        dis_t, had_t, x = case["dis_t"], case["had_t"], case["x"]
+        hd = [c.load(t, "f32") for t in dis_t]
+        hh = [c.load(t, "f32") for t in had_t]
+        gd, gh = fkconv.fk_group_create(c.ctx, hd), fkconv.fk_group_create(c.ctx, hh)
+        cv = fkconv.fk_load_covariance(c.ctx, case["Cs"])
+        m, _ = fkconv.fk_mlp_create(c.ctx, x, synth.MLP_H1, synth.MLP_H2, case["pa"], case["pb"])
+        params = dev(case["params"]).requires_grad_(True)
+        f = autograd.mlp_pdf(c.ctx, m, params, 14, len(x))
+        sig = torch.cat([autograd.fk_conv(c.ctx, gd, f), autograd.fk_conv(c.ctx, gh, f)])
+        chi = autograd.fk_chi2(c.ctx, cv, sig, torch.from_numpy(case["D"]).cuda())
+        chi.sum().backward()
+        torch.cuda.synchronize()
+        g_auto = params.grad.double().cpu().numpy()
+        fkconv.fk_mlp_destroy(c.ctx, m)
+        fkconv.fk_unload_covariance(c.ctx, cv)
+        for h in (gd, gh, *hd, *hh):
+            fkconv.fk_unload_table(c.ctx, h)
+    e = oracle.normwise_rel(g_auto.T, g_explicit.T)
+    say(f"autograd chain vs explicit calls: {e:.2e}")
+    assert e <= 1e-6
