@@ -666,13 +666,25 @@ __global__ void __launch_bounds__(64 * S, 1)
     }
     if (w < 4) put(w);
     lds_barrier();
-    const int nb = q.nv1 > 0 ? 2 : 1;
-    for (int b = 0; b < nb; ++b) {
+    // the item's slots, through descriptors over them: a fixed number of
+    // stores on every path (elements past the tile and the slot of an
+    // absent second block are dropped by the descriptors), so the
+    // compiler's waits on the ring do not have to drain it here
+    constexpr int kPer = (16 * RP + NTHR - 1) / NTHR;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
       const float *rb = red + (size_t)b * 4 * 16 * RP;
-      float *dst = part + (size_t)(q.slot + b) * 16 * kRpMax;
-      for (int i = threadIdx.x; i < 16 * RP; i += NTHR) {
-        const int rw = i / RP, col = i - rw * RP;
-        dst[rw * kRpMax + col] = ((rb[i] + rb[16 * RP + i]) + rb[32 * RP + i]) + rb[48 * RP + i];
+      const __amdgpu_buffer_rsrc_t rsd = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(part + (size_t)(q.slot + b) * 16 * kRpMax), (short)0,
+          b == 0 || q.nv1 > 0 ? 16 * kRpMax * 4 : 0, kBufferRsrcWord3);
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * NTHR;
+        const int ii = i < 16 * RP ? i : 0;
+        const int rw = ii / RP, col = ii - rw * RP;
+        const float v = ((rb[ii] + rb[16 * RP + ii]) + rb[32 * RP + ii]) + rb[48 * RP + ii];
+        const unsigned off = i < 16 * RP ? (unsigned)(rw * kRpMax + col) * 4u : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsd, off, 0, 0);
       }
     }
     lds_barrier();
