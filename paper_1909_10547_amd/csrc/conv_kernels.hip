@@ -733,22 +733,47 @@ __global__ void __launch_bounds__(64 * S, 1)
         // sum over the 16 rows of each tile of acc times the weights (the
         // lane's four rows are one 16-byte read of a weight column); the
         // tile of an absent second block is skipped
+        // Each step runs over all column tiles before the next one starts,
+        // so the weight reads and each round of cross-lane adds are issued
+        // together and wait once (per tile they would form one chain of
+        // LDS round trips per job).
         const float *wt = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c * kAdjWRow + 4 * g;
+        float v[NT];
+        if (Cq.nv1 > 0) {
+          f32x4 w0[NT], w1[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            w0[j] = *(const f32x4 *)(wt + 16 * j * kAdjWRow);
+            w1[j] = *(const f32x4 *)(wt + 16 * j * kAdjWRow + 16);
+          }
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            v[j] = (((acc0[j][0] * w0[j][0] + acc0[j][1] * w0[j][1]) + acc0[j][2] * w0[j][2]) +
+                    acc0[j][3] * w0[j][3]) +
+                   (((acc1[j][0] * w1[j][0] + acc1[j][1] * w1[j][1]) + acc1[j][2] * w1[j][2]) +
+                    acc1[j][3] * w1[j][3]);
+        } else {
+          f32x4 w0[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) w0[j] = *(const f32x4 *)(wt + 16 * j * kAdjWRow);
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            v[j] = ((acc0[j][0] * w0[j][0] + acc0[j][1] * w0[j][1]) + acc0[j][2] * w0[j][2]) +
+                   acc0[j][3] * w0[j][3];
+        }
+        float u[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) u[j] = __shfl_xor(v[j], 16);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) v[j] += u[j];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) u[j] = __shfl_xor(v[j], 32);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-          const f32x4 w0 = *(const f32x4 *)(wt + 16 * j * kAdjWRow);
-          float v = ((acc0[j][0] * w0[0] + acc0[j][1] * w0[1]) + acc0[j][2] * w0[2]) +
-                    acc0[j][3] * w0[3];
-          if (Cq.nv1 > 0) {
-            const f32x4 w1 = *(const f32x4 *)(wt + 16 * j * kAdjWRow + 16);
-            v += ((acc1[j][0] * w1[0] + acc1[j][1] * w1[1]) + acc1[j][2] * w1[2]) +
-                 acc1[j][3] * w1[3];
-          }
-          v += __shfl_xor(v, 16);
-          v += __shfl_xor(v, 32);
+          v[j] += u[j];
           // branch-free: both rows are updated, one of them by zero
-          gr0[j] += g == c_k ? v : 0.f;
-          gr1[j] += g == c_k - 4 ? v : 0.f;
+          gr0[j] += g == c_k ? v[j] : 0.f;
+          gr1[j] += g == c_k - 4 ? v[j] : 0.f;
         }
       } else {
         const float *fl = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c_al * RP + c;
