@@ -220,7 +220,7 @@ struct FlatPairs {
   int16_t ab[kFlatMaxPairs];
 };
 // Launch shape of out[N][R] = FK[N][K] L[K][R]: the matrix-core kernel
-// (64 x 64 tiles) or the streaming kernel (nb rows x cw*vec columns), K split
+// (128 x 128 tiles) or the streaming kernel (nb rows x cw*vec columns), K split
 // into ks chunks of kchunk (partial sums in a workspace when ks > 1).
 struct FlatPlan {
   bool mfma = false;

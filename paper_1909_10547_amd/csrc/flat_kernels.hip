@@ -15,8 +15,8 @@
 //    accumulates the block's rows of its column over k = lane (mod lanes),
 //    and the lanes are combined by a fixed tree in LDS.
 //  * flat_mfma_kernel: N > 16 and R > 16, a dense product on the matrix
-//    cores: 64 x 64 output tiles per workgroup (2 x 2 waves of 32 x 32),
-//    k-steps of 16 staged through LDS, v_mfma_f32_16x16x4f32.
+//    cores: 128 x 128 output tiles per workgroup (2 x 2 waves of 64 x 64),
+//    stages of 32 k double-buffered through LDS, v_mfma_f32_16x16x4f32.
 // Both write partial sums per K-chunk when K is split over workgroups;
 // flat_reduce_kernel adds the chunks in order.
 #include <algorithm>
@@ -115,56 +115,110 @@ __global__ void __launch_bounds__(kFlatThreads)
   }
 }
 
-// 64 x 64 output tile per workgroup, K-chunk blockIdx.z; see the file comment.
-constexpr int kMT = 64, kBK = 16, kPad = 68;
+// 128 x 128 output tile per workgroup, K-chunk blockIdx.z; see the file
+// comment.  Four waves in 2 x 2, each 64 x 64 = 4 x 4 tiles of
+// v_mfma_f32_16x16x4f32.  K advances in stages of 32 through two LDS
+// buffers: the global loads of stage s + 1 are in flight while stage s is
+// multiplied, and one barrier per stage separates the two.  Inside a stage,
+// k-step q of lane group g takes k = 16 (q / 4) + 4 g + q % 4 (any order
+// that A and B share is the same sum), so a lane reads its A values of four
+// k-steps as one 16-byte LDS read.  VB = 4 loads L in 16-byte vectors (R %
+// 4 == 0 and a 16-byte aligned L), VB = 1 element by element.
+constexpr int kMT = 128, kBK = 32, kApad = kBK + 4, kBpad = kMT + 4;
 
+template <int VB>
 __global__ void __launch_bounds__(kFlatThreads)
     flat_mfma_kernel(const float *__restrict__ fk, const float *__restrict__ lum, int64_t N,
                      int64_t K, int64_t R, int64_t kchunk, float *__restrict__ part) {
-  __shared__ float As[kBK][kPad];  // [k][row]
-  __shared__ float Bs[kBK][kPad];  // [k][column]
+  __shared__ __attribute__((aligned(16))) float As[2][kMT][kApad];  // [row][k]
+  __shared__ __attribute__((aligned(16))) float Bs[2][kBK][kBpad];  // [k][column]
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, g = lane >> 4, l16 = lane & 15;
   const int64_t m0 = (int64_t)blockIdx.y * kMT, c0 = (int64_t)blockIdx.x * kMT;
   const int64_t ks = (int64_t)blockIdx.z * kchunk, ke = std::min(K, ks + kchunk);
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  f32x4 acc[2][2];
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  // A: thread t loads k = t % 32 of rows t / 32 + 8 p; B: k-row t / 32 + 8 p
+  // (VB = 4: columns 4 (t % 32) .. + 3; VB = 1: columns t % 32 + 32 j)
+  const int ak = t & 31, ar = t >> 5;
+  constexpr int kBL = VB == 4 ? 4 : 16;
+  float ra[16], rb[kBL * VB];
+  auto load = [&](int64_t kk) {
+    const int64_t gk = kk + ak;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t kk = ks; kk < ke; kk += kBK) {
-    // A tile: 64 rows x 16 k; B tile: 16 k x 64 columns; zero outside
-#pragma unroll
-    for (int j = 0; j < kMT * kBK / kFlatThreads; ++j) {
-      const int e = t + kFlatThreads * j;
-      const int row = e / kBK, kc = e % kBK;
-      const int64_t gr = m0 + row, gk = kk + kc;
-      As[kc][row] = gr < N && gk < ke ? fk[gr * K + gk] : 0.f;
-      const int kr = e / kMT, cc = e % kMT;
-      const int64_t gk2 = kk + kr, gc = c0 + cc;
-      Bs[kr][cc] = gk2 < ke && gc < R ? lum[gk2 * R + gc] : 0.f;
+    for (int p = 0; p < 16; ++p) {
+      const int64_t gr = m0 + ar + 8 * p;
+      ra[p] = gr < N && gk < ke ? fk[gr * K + gk] : 0.f;
     }
-    __syncthreads();
+    if (VB == 4) {
 #pragma unroll
-    for (int kq = 0; kq < kBK; kq += 4) {
-      float a[2], b[2];
+      for (int p = 0; p < 4; ++p) {
+        const int64_t gk2 = kk + ar + 8 * p, gc = c0 + 4 * ak;
+        const float4 v = gk2 < ke && gc < R ? *(const float4 *)(lum + gk2 * R + gc) : float4{0.f, 0.f, 0.f, 0.f};
+        rb[4 * p] = v.x;
+        rb[4 * p + 1] = v.y;
+        rb[4 * p + 2] = v.z;
+        rb[4 * p + 3] = v.w;
+      }
+    } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kq + g][wm + 16 * i + l16];
+      for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kq + g][wn + 16 * j + l16];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          const int64_t gk2 = kk + ar + 8 * p, gc = c0 + ak + 32 * j;
+          rb[4 * p + j] = gk2 < ke && gc < R ? lum[gk2 * R + gc] : 0.f;
+        }
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < 16; ++p) As[buf][ar + 8 * p][ak] = ra[p];
+    if (VB == 4) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        *(f32x4 *)&Bs[buf][ar + 8 * p][4 * ak] = f32x4{rb[4 * p], rb[4 * p + 1], rb[4 * p + 2], rb[4 * p + 3]};
+    } else {
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bs[buf][ar + 8 * p][ak + 32 * j] = rb[4 * p + j];
+    }
+  };
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nst = (int)((ke - ks + kBK - 1) / kBK);
+  load(ks);
+  store(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) load(ks + (int64_t)(st + 1) * kBK);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f32x4 a[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = *(const f32x4 *)&As[buf][wm + 16 * i + l16][16 * h + 4 * g];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Bs[buf][16 * h + 4 * g + q][wn + 16 * j + l16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][q], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (st + 1 < nst) store(buf ^ 1);
     __syncthreads();
   }
   float *dst = part + (int64_t)blockIdx.z * N * R;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t row = m0 + wm + 16 * i + 4 * g + q, col = c0 + wn + 16 * j + l16;
@@ -205,7 +259,7 @@ FlatPlan flat_plan(int64_t N, int64_t K, int64_t R, int ncu) {
     p.gx = (R + kMT - 1) / kMT;
     p.gy = (N + kMT - 1) / kMT;
     tiles = p.gx * p.gy;
-    min_chunk = 1024;
+    min_chunk = 4 * kBK;  // at least four stages per workgroup
   } else {
     p.nb = N <= 8 ? 8 : 16;
     p.cw = 1;
@@ -217,8 +271,9 @@ FlatPlan flat_plan(int64_t N, int64_t K, int64_t R, int ncu) {
     tiles = p.gx * p.gy;
     min_chunk = 16 * (kFlatThreads / p.cw);  // at least 16 k per thread
   }
-  // split K until the grid has about 16 workgroups per compute unit
-  const int64_t want = 16LL * ncu;
+  // split K until the grid has about 16 workgroups per compute unit (4 for
+  // the matrix-core tiles, which hold 2 per unit at a time)
+  const int64_t want = (p.mfma ? 4LL : 16LL) * ncu;
   int64_t ks = std::max<int64_t>(1, want / std::max<int64_t>(tiles, 1));
   ks = std::min<int64_t>(ks, std::max<int64_t>(1, (K + min_chunk - 1) / min_chunk));
   ks = std::min<int64_t>(ks, 65535);
@@ -247,8 +302,12 @@ hipError_t launch_flat(const FlatPlan &p, int64_t N, int64_t K, int64_t R, const
   float *part = p.ks > 1 ? work : out;
   const dim3 grid((unsigned)p.gx, (unsigned)p.gy, (unsigned)p.ks);
   if (p.mfma) {
-    hipLaunchKernelGGL(flat_mfma_kernel, grid, dim3(kFlatThreads), 0, s, fk, lum, N, K, R,
-                       p.kchunk, part);
+    if (R % 4 == 0 && ((uintptr_t)lum & 15) == 0)
+      hipLaunchKernelGGL(flat_mfma_kernel<4>, grid, dim3(kFlatThreads), 0, s, fk, lum, N, K, R,
+                         p.kchunk, part);
+    else
+      hipLaunchKernelGGL(flat_mfma_kernel<1>, grid, dim3(kFlatThreads), 0, s, fk, lum, N, K, R,
+                         p.kchunk, part);
   } else {
 #define FK_FLAT(NB, CW)                                                                          \
   if (p.vec == 4)                                                                                  \
