@@ -33,6 +33,7 @@ METRIC = "hadronic FK-conv datapoint·replicas/s bf16 vs fp32 @rel≤5e-3; p50/p
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2516.6
 COUNTERS = os.path.join(ROOT, "profiles", "had_fwd_bf16_had_fit_counters.json")
+DIS_COUNTERS = os.path.join(ROOT, "profiles", "dis_fwd_dis_bandwidth_counters.json")
 # the kernel source and the planner that hands it its work lists
 KERNEL_SRC = [os.path.join(ROOT, "paper_1909_10547_amd", "csrc", f)
               for f in ("conv_kernels.hip", "runtime.cpp")]
@@ -147,11 +148,11 @@ def main() -> int:
     ap.add_argument("--profile-adj", action="store_true",
                     help="only load the BF16 tables and run the BF16 hadronic adjoint (for profiler runs)")
     ap.add_argument("--profile-dis", action="store_true",
-                    help="only the DIS bandwidth set, BF16, R=1 (for profiler runs)")
+                    help="only the DIS bandwidth set, BF16 (FP32 with --profile-f32), R=1 (for profiler runs)")
     ap.add_argument("--profile-nrep", type=int, default=0,
                     help="replica count of the --profile-bf16/--profile-adj runs (default: the workload's)")
     ap.add_argument("--profile-f32", action="store_true",
-                    help="with --profile-bf16/--profile-adj: load and run the FP32 tables instead")
+                    help="with --profile-bf16/--profile-adj/--profile-dis: load and run the FP32 tables instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 1 GiB three times (HBM byte-counter calibration)")
     args = ap.parse_args()
@@ -180,7 +181,7 @@ def main() -> int:
         scale = args.dis_hbm_gib * (1 << 30) / (9 * 50 * 4 * sum(base.ndata))
         wd = synth.dis_fit_workload(scale)
         c = fkconv.Context(0)
-        hs = [c.load(wd.table(d), "bf16") for d in range(len(wd.ndata))]
+        hs = [c.load(wd.table(d), "f32" if args.profile_f32 else "bf16") for d in range(len(wd.ndata))]
         g = fkconv.fk_group_create(c.ctx, hs)
         x = torch.from_numpy(wd.pdf(1).astype(np.float32)).cuda()
         for _ in range(args.warmup + args.steps):
@@ -727,6 +728,12 @@ def dis_hbm(c, args, torch, fkconv, synth):
     N = sum(t.ndata for t in tabs)
     elems = sum(t.fk.size for t in tabs)
     out = {"ndata": N, "fk_elements": elems, "peak_gbs": PEAK_HBM_GBS}
+    try:
+        dis_counters = json.load(open(DIS_COUNTERS))
+        if dis_counters.get("kernel_sha256_16") != kernel_hash():
+            dis_counters = None
+    except (OSError, ValueError):
+        dis_counters = None
     for fmt, nbytes in (("f32", 4), ("bf16", 2)):
         hs = [c.load(t, fmt) for t in tabs]
         g = fkconv.fk_group_create(c.ctx, hs)
@@ -745,6 +752,12 @@ def dis_hbm(c, args, torch, fkconv, synth):
                                   "achieved_gbs": byt / (kms * 1e-3) / 1e9,
                                   "frac": byt / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                   "value": N * R / (ms * 1e-3)}
+            if R == 1 and dis_counters:
+                # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE (calibrated),
+                # over this run's kernel time
+                hb = dis_counters["rows"][fmt]["hbm_bytes_per_launch"]
+                out[f"{fmt}_R{R}"]["hbm_bytes_from_counters"] = hb
+                out[f"{fmt}_R{R}"]["hbm_gbs_from_counters"] = hb / (kms * 1e-3) / 1e9
         fkconv.fk_unload_table(c.ctx, g)
         for h in hs:
             fkconv.fk_unload_table(c.ctx, h)
