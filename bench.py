@@ -322,6 +322,37 @@ def main() -> int:
         },
     }
 
+    # outputs of the rows below that the CPU-baseline leg checks against FP64
+    checks = []
+    if not args.no_peaks:
+        log("measured ceilings: HBM copy, BF16 GEMM")
+        pk = measured_peaks(torch)
+        pk["mfma_bf16_register_tflops"] = fkconv.fk_measure_mfma_peak(c.ctx)
+        pk["note"] += "; register-only v_mfma_f32_16x16x32_bf16 loop (fk_measure_mfma_peak)"
+        result["measured_peaks"] = pk
+        result["roofline"]["mfma_frac_of_register_peak"] = (result["roofline"]["mfma_tflops"] /
+                                                            pk["mfma_bf16_register_tflops"])
+        result["roofline"]["frac_of_measured"] = achieved / pk["hbm_copy_gbs"]
+    if not args.no_rsweep:
+        log("replica sweep")
+        result.setdefault("rows", {})["had_bf16_rsweep"] = rsweep(c, w, gb, elems_fwd, Ntot, args, torch,
+                                                                  fkconv)
+    if not args.no_extras:
+        log("extra rows: DIS, adjoints, chi2, fit step")
+        result.setdefault("rows", {}).update(extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv,
+                                                    synth, checks))
+    if not args.no_table3:
+        log("Table 3 shapes (flattened form)")
+        result.setdefault("rows", {})["table3"] = table3(c, args, torch, fkconv, synth, checks)
+    if not args.no_serve:
+        log("serving")
+        result.setdefault("rows", {})["serving"] = serving(c, w, tabs, args, torch, fkconv, synth, checks)
+    if not args.no_dis_hbm:
+        log("large DIS set for HBM bandwidth")
+        result.setdefault("rows", {})["dis_hbm"] = dis_hbm(c, args, torch, fkconv, synth)
+
+    # The CPU-baseline leg: the FP64 oracle timed on the host (every datapoint
+    # of the headline workload) and every error against FP64 in this line.
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline: the FP64 oracle on every datapoint (errors per dataset)")
@@ -391,33 +422,8 @@ def main() -> int:
                                                    if l.startswith("model name")][0]
         except (OSError, IndexError):
             pass
-
-    if not args.no_peaks:
-        log("measured ceilings: HBM copy, BF16 GEMM")
-        pk = measured_peaks(torch)
-        pk["mfma_bf16_register_tflops"] = fkconv.fk_measure_mfma_peak(c.ctx)
-        pk["note"] += "; register-only v_mfma_f32_16x16x32_bf16 loop (fk_measure_mfma_peak)"
-        result["measured_peaks"] = pk
-        result["roofline"]["mfma_frac_of_register_peak"] = (result["roofline"]["mfma_tflops"] /
-                                                            pk["mfma_bf16_register_tflops"])
-        result["roofline"]["frac_of_measured"] = achieved / pk["hbm_copy_gbs"]
-    if not args.no_rsweep:
-        log("replica sweep")
-        result.setdefault("rows", {})["had_bf16_rsweep"] = rsweep(c, w, gb, elems_fwd, Ntot, args, torch,
-                                                                  fkconv)
-    if not args.no_extras:
-        log("extra rows: DIS, adjoints, chi2, fit step")
-        result.setdefault("rows", {}).update(extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv,
-                                                    synth))
-    if not args.no_table3:
-        log("Table 3 shapes (flattened form)")
-        result.setdefault("rows", {})["table3"] = table3(c, args, torch, fkconv, synth)
-    if not args.no_serve:
-        log("serving")
-        result.setdefault("rows", {})["serving"] = serving(c, w, tabs, args, torch, fkconv, synth)
-    if not args.no_dis_hbm:
-        log("large DIS set for HBM bandwidth")
-        result.setdefault("rows", {})["dis_hbm"] = dis_hbm(c, args, torch, fkconv, synth)
+        # every other row's outputs against FP64
+        fp64_checks(result, checks, oracle, normwise)
 
     fkconv.fk_unload_table(c.ctx, gb)
     fkconv.fk_unload_table(c.ctx, gf)
@@ -427,7 +433,56 @@ def main() -> int:
     return 0
 
 
-def serving(c, w, had_tabs, args, torch, fkconv, synth):
+def fp64_checks(result, checks, oracle, normwise):
+    """Errors against the FP64 oracle of the rows that appended their outputs
+    to ``checks`` (part of the CPU-baseline leg)."""
+    rows = result.get("rows", {})
+
+    def gradwise(g, ref):
+        # normwise over (flavour, x) per replica column, max over columns
+        F, X, R = ref.shape
+        return normwise(g.reshape(F * X, R), ref.reshape(F * X, R))
+
+    for ck in checks:
+        if ck["type"] == "dis":
+            refs = [oracle.dis(m, fk, ck["pdf"]) for m, fk in ck["tables"]]
+            gref = sum(oracle.dis_grad(m, fk, gb, ck["pdf"].shape[0], ck["pdf"].shape[1])
+                       for (m, fk), gb in zip(ck["tables"],
+                                              np.split(ck["gbar"], np.cumsum([fk.shape[0] for _, fk in ck["tables"]])[:-1])))
+            offs = np.cumsum([0] + [r.shape[0] for r in refs])
+            for fmt, y in ck["out"].items():
+                per = [normwise(y[o:o + r.shape[0]], r) for o, r in zip(offs, refs)]
+                rows[f"dis_{fmt}"]["error_vs_fp64"] = {
+                    "rows": "all", "max_over_datasets": max(per), "all": normwise(y, np.concatenate(refs)),
+                    "adjoint_normwise": gradwise(ck["grad"][fmt], gref),
+                    "adjoint_weights": "seeded normal weights on every datapoint"}
+        elif ck["type"] == "had_grad":
+            gref = sum(oracle.had_grad(m, fk, ck["pdf"], gb) for (m, fk), gb in zip(ck["tables"], ck["gbar"]))
+            for fmt, g in ck["grad"].items():
+                rows[f"had_adjoint_{fmt}"]["error_vs_fp64"] = {
+                    "normwise": gradwise(g, gref),
+                    "weights": "seeded normal weights on 12 evenly spaced rows of every dataset, zero elsewhere"}
+        elif ck["type"] == "chi2":
+            Ls = [oracle.cholesky(C) for C in ck["C"]]
+            ref, dref = oracle.chi2(Ls, ck["sigma"], ck["D"])
+            rows["chi2_fp64"]["error_vs_fp64"] = {
+                "chi2_max_rel": float(np.max(np.abs(ck["chi2"] - ref) / np.abs(ref))),
+                "gradient_normwise": normwise(ck["grad"], dref),
+                "note": "gradient returned in FP32"}
+        elif ck["type"] == "flat":
+            ref = oracle.flat_conv(ck["fk"], oracle.luminosity(ck["mask"], ck["pdf"]))
+            rows["table3"][ck["index"]]["error_vs_fp64"] = {
+                "sampled_outputs": list(ck["y"].shape),
+                "max_abs_over_max_ref": float(np.max(np.abs(ck["y"] - ref)) / np.max(np.abs(ref)))}
+        elif ck["type"] == "serving":
+            err = 0.0
+            for kind, m, fk, pdf, y in ck["items"]:
+                ref = oracle.had(m, fk, pdf) if kind == "had" else oracle.dis(m, fk, pdf)
+                err = max(err, oracle.normwise_rel(y, ref))
+            rows["serving"]["error"]["fp32_reference_vs_fp64_max_normwise"] = err
+
+
+def serving(c, w, had_tabs, args, torch, fkconv, synth, checks):
     """Continuous batching: the table catalogue of the serving workload (the
     20 DIS and 10 hadronic datasets plus two DIS and two hadronic tables with
     N = 2000), BF16 with FP32 fallback copies; each BF16 table is probed
@@ -437,8 +492,8 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
     closed-loop (everything submitted at once), then Poisson streams at
     fractions of it; latency = submit -> completion seen by the loop.
     Afterwards every request of the last stream is re-run alone (bitwise
-    equality is required) and its error is measured."""
-    import oracle
+    equality is required) and its error is measured (against FP64 in the
+    CPU-baseline leg, from the data this function appends to ``checks``)."""
     sw = synth.serving_workload(1.0)
     cat = list(sw.catalogue())
     hb, hf = [], []
@@ -527,17 +582,14 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
         (err_f if prec[i] == fkconv.FK_F32 else err_b).append(e)
     if differ:
         raise RuntimeError(f"serving: {differ} of {len(outs)} requests differ from their alone runs")
-    ref_err = 0.0
+    items = []
     for (ti, R, k), y in ref32.items():
         t = cat[ti][1]
         pdf = pools[R][k].double().cpu().numpy()
-        if kinds[ti] == "had":
-            sel = np.unique(np.linspace(0, t.ndata - 1, 16).astype(int))
-            ref = oracle.had(t.mask, t.fk[sel], pdf)
-        else:
-            sel = np.arange(t.ndata)
-            ref = oracle.dis(t.mask, t.fk, pdf)
-        ref_err = max(ref_err, oracle.normwise_rel(y.double().cpu().numpy()[sel], ref))
+        sel = (np.unique(np.linspace(0, t.ndata - 1, 16).astype(int)) if kinds[ti] == "had"
+               else np.arange(t.ndata))
+        items.append((kinds[ti], t.mask, t.fk[sel], pdf, y.double().cpu().numpy()[sel]))
+    checks.append({"type": "serving", "items": items})
     res["alone_equals_mix"] = f"all {len(outs)} requests of the last stream bitwise equal to their alone runs"
     res["error"] = {
         "bf16_requests_max_normwise": float(max(err_b)) if err_b else None,
@@ -546,7 +598,7 @@ def serving(c, w, had_tabs, args, torch, fkconv, synth):
         "requests": len(outs),
         "reference": "each request's FP32 alone run; FP32 vs the FP64 oracle over every distinct "
                      "(table, PDF batch): DIS every row, hadronic 16 evenly spaced rows",
-        "fp32_reference_vs_fp64_max_normwise": ref_err,
+        "fp32_reference_vs_fp64_max_normwise": None,
     }
     for h in hb + hf:
         fkconv.fk_unload_table(c.ctx, h)
@@ -574,7 +626,7 @@ TABLE3 = [
 ]
 
 
-def table3(c, args, torch, fkconv, synth):
+def table3(c, args, torch, fkconv, synth, checks):
     """Every row of Table 3 in the flattened form the paper times: FK [N][K]
     against a PDF matrix [K][R].  For K = 35721 the matrix is the luminosity
     of 49 flavour pairs on 27 grid points, formed on the device from the PDF;
@@ -651,6 +703,13 @@ def table3(c, args, torch, fkconv, synth):
             row["with_h2d_pdf_s"] = med(with_h2d_pdf)
         best = min(v for v in paper if v is not None)
         row["paper_best_over_with_h2d"] = best / t_h2d
+        if lumi:
+            # sampled outputs for the FP64 check (16 rows x 8 columns at most)
+            resident()
+            rr = np.unique(np.linspace(0, N - 1, min(N, 16)).astype(int))
+            cc = np.unique(np.linspace(0, R - 1, min(R, 8)).astype(int))
+            checks.append({"type": "flat", "index": len(rows), "mask": mask, "fk": fk_h.numpy()[rr],
+                           "pdf": pdf_h.numpy()[:, :, cc], "y": out_d.double().cpu().numpy()[np.ix_(rr, cc)]})
         rows.append(row)
         log(f"  Table 3 row PDF {K}x{R} FK {N}x{K}: resident {t_res * 1e3:.3f} ms, with H2D "
             f"{t_h2d * 1e3:.3f} ms (paper best {best:.3g} s)")
@@ -764,7 +823,9 @@ def dis_hbm(c, args, torch, fkconv, synth):
     return out
 
 
-def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
+def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth, checks):
+    """Rows beyond the headline; the outputs that the CPU-baseline leg checks
+    against FP64 are appended to ``checks``."""
     rows = {}
     # DIS global-like workload (20 datasets, R=100)
     w1 = synth.dis_fit_workload(args.scale)
@@ -772,6 +833,7 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
     Nd = sum(t.ndata for t in dtabs)
     x1 = torch.from_numpy(w1.pdf(R).astype(np.float32)).cuda()
     dis_centrals = []
+    dis_out, dis_grad = {}, {}
     for fmt in ("bf16", "f32"):
         hs = [c.load(t, fmt) for t in dtabs]
         g = fkconv.fk_group_create(c.ctx, hs)
@@ -784,6 +846,11 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
                               "kernel_ms": fwd_kernel(kt, "dis")[0] / max(fwd_kernel(kt, "dis")[1], 1),
                               "kernel": fwd_kernel(kt, "dis")[2],
                               "value": Nd * R / (ms * 1e-3), "adjoint_ms": msb}
+        # outputs and gradients (seeded weights) for the FP64 check
+        gw = torch.from_numpy(np.random.default_rng(11).standard_normal((Nd, R)).astype(np.float32)).cuda()
+        dis_out[fmt] = out.double().cpu().numpy()
+        dis_grad[fmt] = fkconv.fk_conv_backward(c.ctx, g, None, gw).double().cpu().numpy()
+        dis_gw = gw.double().cpu().numpy()
         if fmt == "f32":
             cen = fkconv.fk_conv_dis(c.ctx, g, x1[:, :, :1].contiguous())[:, 0].double().cpu().numpy()
             off = 0
@@ -793,6 +860,8 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
         fkconv.fk_unload_table(c.ctx, g)
         for h in hs:
             fkconv.fk_unload_table(c.ctx, h)
+    checks.append({"type": "dis", "tables": [(t.mask, t.fk) for t in dtabs],
+                   "pdf": x1.double().cpu().numpy(), "out": dis_out, "grad": dis_grad, "gbar": dis_gw})
     # hadronic forward with FP8 (e4m3) tables: half the bytes of BF16, but
     # three mantissa bits, so outside the 5e-3 accuracy gate
     h8 = [c.load(t, "e4m3") for t in tabs]
@@ -828,6 +897,23 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
                                       "table_bytes": elems_full * (2 if fmt == "bf16" else 4),
                                       "achieved_gbs": elems_full * (2 if fmt == "bf16" else 4)
                                       / (kt[kn][0] / max(kt[kn][1], 1) * 1e-3) / 1e9}
+    # gradient of 12 evenly spaced rows of every dataset (seeded weights on
+    # those rows, zero elsewhere) for the FP64 check
+    rng = np.random.default_rng(12)
+    gs = np.zeros((Ntot, R), dtype=np.float32)
+    sels, off = [], 0
+    for t in tabs:
+        sel = np.unique(np.linspace(0, t.ndata - 1, 12).astype(int))
+        gs[off + sel] = rng.standard_normal((len(sel), R)).astype(np.float32)
+        sels.append(sel)
+        off += t.ndata
+    gsd = torch.from_numpy(gs).cuda()
+    offs = np.cumsum([0] + [t.ndata for t in tabs])
+    checks.append({"type": "had_grad", "tables": [(t.mask, t.fk[sel]) for t, sel in zip(tabs, sels)],
+                   "gbar": [gs[o + sel].astype(np.float64) for o, sel in zip(offs, sels)],
+                   "pdf": x.double().cpu().numpy(),
+                   "grad": {fmt: fkconv.fk_conv_backward(c.ctx, g, x, gsd).double().cpu().numpy()
+                            for fmt, g in (("bf16", gb), ("f32", gf))}})
     # FP64 chi2 over the datasets of both workloads (block-diagonal covariance)
     had_c = fkconv.fk_conv_had(c.ctx, gf, x[:, :, :1].contiguous())
     blocks, centrals, off = [], [], 0
@@ -842,6 +928,9 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth):
     sig = torch.randn((Nall, R), dtype=torch.float32, device="cuda")
     ms, _ = time_steps(lambda: fkconv.fk_chi2(c.ctx, cv, sig, D), args.steps, args.warmup, torch)
     rows["chi2_fp64"] = {"ndata": Nall, "blocks": len(Cs), "ms_per_step": ms}
+    chi_g, dchi_g = fkconv.fk_chi2(c.ctx, cv, sig, D)
+    checks.append({"type": "chi2", "C": Cs, "D": np.concatenate(Ds), "sigma": sig.double().cpu().numpy(),
+                   "chi2": chi_g.cpu().numpy(), "grad": dchi_g.double().cpu().numpy()})
     # full fit step: DIS + hadronic forward (bf16), chi2, both adjoints
     hs = [c.load(t, "bf16") for t in dtabs]
     gd = fkconv.fk_group_create(c.ctx, hs)
