@@ -114,6 +114,7 @@ struct DisStreamWG {
 constexpr int kDisStreamW = 16;      // k-steps in flight per wave
 constexpr int kDisStreamWaves = 8;   // waves per workgroup
 constexpr int kDisStreamMaxBlk = 512;  // blocks per workgroup (scales kept in LDS)
+constexpr int kDisStreamMinBlk = 4;    // blocks per workgroup at least (amortise the B staging)
 
 // Hadronic adjoint item: one group, blocks [block0, block1) of its table.
 struct HadAdjItem {

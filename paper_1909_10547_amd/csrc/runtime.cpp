@@ -422,8 +422,13 @@ static fk_status build_plan(fk_ctx *c, Plan &p, const std::vector<Table *> &ts) 
     int ttot_max = 0;
     long total_blk = 0;
     for (auto *t : ts) total_blk += (t->N + 15) / 16;
-    const int target =
-        (int)std::max<long>(1, std::min<long>(kDisStreamMaxBlk, (total_blk + 8 * ncu - 1) / (8 * ncu)));
+    // at least kDisStreamMinBlk blocks per range: a workgroup stages the B
+    // operands of all its table's groups before it streams, which a single
+    // block does not amortise (measured on the DIS global workload, 400
+    // blocks, R=100: 20.9 -> 16.4 us BF16 and 71 -> 43 us FP32 per step
+    // with 4 instead of 1; 2 to 4 alike, 6 and 8 slower in FP32)
+    const int target = (int)std::max<long>(
+        kDisStreamMinBlk, std::min<long>(kDisStreamMaxBlk, (total_blk + 8 * ncu - 1) / (8 * ncu)));
     for (size_t t = 0; t < ts.size(); ++t) {
       const int g0 = (int)dgroups.size();
       int ttot = 0;
