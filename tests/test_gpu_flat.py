@@ -107,6 +107,33 @@ def test_flattened_form_equals_eq1():
     assert e <= 1e-5
 
 
+def test_flat_conv_unaligned_matrix_takes_the_element_path():
+    """R % 4 == 0 but L starts 4 bytes past a 16-byte boundary: the
+    matrix-core product must load L element by element and give the same sums
+    (the k order does not depend on how L is loaded)."""
+    N, K, R = 130, 3001, 200
+    rng = np.random.default_rng(9)
+    fk = rng.standard_normal((N, K)).astype(np.float32)
+    L = rng.uniform(0, 2, size=(K, R)).astype(np.float32)
+    with fkconv.Context(0) as c:
+        buf = torch.empty(K * R + 4, dtype=torch.float32, device="cuda")
+        Lu = buf[1:1 + K * R].view(K, R)
+        Lu.copy_(dev(L))
+        assert Lu.data_ptr() % 16 == 4
+        say(f"case N={N} K={K} R={R}, L at a 4-byte offset")
+        y = fkconv.fk_flat_conv(c.ctx, dev(fk), Lu)
+        ya = fkconv.fk_flat_conv(c.ctx, dev(fk), dev(L))
+        h = chain(c, N, K, R)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ya), "aligned and unaligned L give different sums"
+        got = y.double().cpu().numpy()
+    ref = oracle.flat_conv(fk, L)
+    absterms = oracle.flat_conv(np.abs(fk), np.abs(L))
+    comp = float(np.max(np.abs(got - ref) / absterms))
+    say(f"  per element {comp:.2e} of sum|terms| (bound {gamma(h):.2e})")
+    assert comp <= gamma(h)
+
+
 @pytest.mark.parametrize("N,K,R", [(8, 10 ** 8, 1), (10, 35721, 50000), (2000, 35721, 2000),
                                    (10 ** 4, 35721, 1)])
 def test_table3_full_size_sampled(N, K, R):
