@@ -414,6 +414,9 @@ def main() -> int:
             "bf16_vs_fp64_max_over_datasets": worst_b,
             "fp32_vs_fp64_max_over_datasets": max(e["fp32"] for e in per_ds),
             "per_dataset": per_ds,
+            "elementwise_bf16": oracle.error_report(gotb, ref),
+            "elementwise_fp32": oracle.error_report(gotf, ref),
+            "elementwise_note": "relative error of the outputs with |y*| >= 1e-3 max|y*|: p50, p99, max",
             "gate": "normwise per replica column, max over columns, per dataset: bf16 <= 5e-3, fp32 <= 1e-5",
             "gate_met": bool(worst_b <= 5e-3 and max(e["fp32"] for e in per_ds) <= 1e-5),
         })
