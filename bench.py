@@ -846,6 +846,7 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth, checks):
         gout = torch.ones((Nd, R), dtype=torch.float32, device="cuda")
         msb, _ = time_steps(lambda: fkconv.fk_conv_backward(c.ctx, g, None, gout), args.steps, args.warmup, torch)
         rows[f"dis_{fmt}"] = {"ndata": Nd, "ms_per_step": ms, "p50_ms": float(np.median(per)),
+                              "p99_ms": float(np.percentile(per, 99)),
                               "kernel_ms": fwd_kernel(kt, "dis")[0] / max(fwd_kernel(kt, "dis")[1], 1),
                               "kernel": fwd_kernel(kt, "dis")[2],
                               "value": Nd * R / (ms * 1e-3), "adjoint_ms": msb}
@@ -951,6 +952,7 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth, checks):
 
     ms, per = time_steps(fit_step, args.steps, args.warmup, torch)
     rows["fit_step_bf16"] = {"ms_per_step": ms, "p50_ms": float(np.median(per)),
+                             "p99_ms": float(np.percentile(per, 99)),
                              "note": "DIS + hadronic forward, FP64 chi2 with gradient, both adjoints"}
     # the whole descent step on the device: network PDF on the x-grid, the
     # step above, the reverse pass through the network, the update
@@ -977,7 +979,8 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth, checks):
     descent_step()
     lr[0] = 1e-3 / float(gpar.abs().max())
     ms, per = time_steps(descent_step, args.steps, args.warmup, torch)
-    rows["descent_step_bf16"] = {"ms_per_step": ms, "p50_ms": float(np.median(per)), "replicas": R,
+    rows["descent_step_bf16"] = {"ms_per_step": ms, "p50_ms": float(np.median(per)),
+                                 "p99_ms": float(np.percentile(per, 99)), "replicas": R,
                                  "network": f"(x, ln x) -> {synth.MLP_H1} tanh -> {synth.MLP_H2} tanh -> 14, "
                                             f"{P} parameters per replica",
                                  "note": "network PDF, DIS + hadronic forward (BF16 tables), FP64 chi2, both "
