@@ -841,7 +841,9 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth, checks):
         hs = [c.load(t, fmt) for t in dtabs]
         g = fkconv.fk_group_create(c.ctx, hs)
         out = torch.empty((Nd, R), dtype=torch.float32, device="cuda")
-        ms, per = time_steps(lambda: fkconv.fk_conv_dis(c.ctx, g, x1, out=out), args.steps, args.warmup, torch)
+        # microsecond-scale steps: ten times the step count (1000 by default)
+        ms, per = time_steps(lambda: fkconv.fk_conv_dis(c.ctx, g, x1, out=out), 10 * args.steps, args.warmup,
+                             torch)
         kt = kernel_times(c, lambda: fkconv.fk_conv_dis(c.ctx, g, x1, out=out), args.steps, torch, fkconv)
         gout = torch.ones((Nd, R), dtype=torch.float32, device="cuda")
         msb, _ = time_steps(lambda: fkconv.fk_conv_backward(c.ctx, g, None, gout), args.steps, args.warmup, torch)
