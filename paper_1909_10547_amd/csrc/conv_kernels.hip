@@ -19,8 +19,10 @@
 //  adjoints (Table 1, "Gradient"):  DIS g = sum_i FK_i gbar_i,
 //    hadronic g[p,r] = sum_i gbar[i,r] s_i (Shat_i f)[p,r]  -- the same MFMA
 //    product as the forward pass with a different epilogue.
-// All partial sums are written to slots and reduced in a fixed order, so
-// results are bitwise reproducible and independent of batch composition.
+// Where a row's sum is split over workgroups, the parts go to slots that
+// are reduced in a fixed order (the DIS stream kernel writes whole rows
+// itself), so results are bitwise reproducible and independent of batch
+// composition.
 #include <algorithm>
 #include <mutex>
 
@@ -731,12 +733,11 @@ __global__ void __launch_bounds__(64 * S, 1)
     if (job_end) {
       if (ADJ) {
         // sum over the 16 rows of each tile of acc times the weights (the
-        // lane's four rows are one 16-byte read of a weight column); the
-        // tile of an absent second block is skipped
-        // Each step runs over all column tiles before the next one starts,
-        // so the weight reads and each round of cross-lane adds are issued
-        // together and wait once (per tile they would form one chain of
-        // LDS round trips per job).
+        // lane's four rows are one 16-byte read of a weight column; the
+        // tile of an absent second block is skipped).  Each step runs over
+        // all column tiles before the next one starts, so the weight reads
+        // and each round of cross-lane adds are issued together and wait
+        // once (per tile they would form one chain of LDS round trips).
         const float *wt = (const float *)(lds + cpar * bufsz + 4 * Cq.T * RP) + c * kAdjWRow + 4 * g;
         float v[NT];
         if (Cq.nv1 > 0) {
