@@ -987,6 +987,15 @@ def extras(c, w, tabs, gb, gf, x, out_b, R, args, torch, fkconv, synth, checks):
                                             f"{P} parameters per replica",
                                  "note": "network PDF, DIS + hadronic forward (BF16 tables), FP64 chi2, both "
                                          "adjoints, reverse pass through the network, gradient-descent update"}
+    # the same step captured once in a HIP graph and replayed (every entry
+    # point of the step only launches kernels: no allocation, no memset)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        descent_step()
+    ms_g, per_g = time_steps(graph.replay, args.steps, args.warmup, torch)
+    rows["descent_step_bf16"].update({"graph_ms_per_step": ms_g, "graph_p50_ms": float(np.median(per_g)),
+                                      "graph_note": "one step captured in a HIP graph, replayed back to back"})
+    del graph
     fkconv.fk_mlp_destroy(c.ctx, m)
     fkconv.fk_unload_table(c.ctx, gd)
     for h in hs:
