@@ -246,6 +246,35 @@ def test_deterministic(ctx):
     np.testing.assert_array_equal(a, b)
 
 
+def test_two_contexts_overlap_on_two_streams():
+    """Two contexts with their own plans and scratch run the same group on
+    two streams at once, ten launches each without synchronising: every
+    result is bitwise the one of a launch alone."""
+    w = synth.had_fit_workload(scale=0.1)
+    tabs = [w.table(d) for d in range(len(w.ndata))]
+    pdf = dev(f32(w.pdf(100)))
+    with fkconv.Context(0) as ca, fkconv.Context(0) as cb:
+        ga = fkconv.fk_group_create(ca.ctx, [ca.load(t, "bf16") for t in tabs])
+        gb = fkconv.fk_group_create(cb.ctx, [cb.load(t, "bf16") for t in tabs])
+        alone = fkconv.fk_conv_had(ca.ctx, ga, pdf)
+        torch.cuda.synchronize()
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        outs = []
+        for _ in range(10):
+            ya = torch.empty_like(alone)
+            yb = torch.empty_like(alone)
+            # allocated on the current stream, used on the side streams
+            sa.wait_stream(torch.cuda.current_stream())
+            sb.wait_stream(torch.cuda.current_stream())
+            fkconv.fk_conv_had(ca.ctx, ga, pdf, out=ya, stream=sa)
+            fkconv.fk_conv_had(cb.ctx, gb, pdf, out=yb, stream=sb)
+            outs += [ya, yb]
+        torch.cuda.synchronize()
+        say(f"two contexts, {len(outs)} overlapping launches on two streams")
+        for y in outs:
+            assert torch.equal(y, alone)
+
+
 def test_error_paths(ctx):
     w = synth.dis_single_workload()
     tab = w.table(0)
