@@ -760,10 +760,13 @@ def measured_peaks(torch):
 
 
 def rsweep(c, w, gb, elems_fwd, Ntot, args, torch, fkconv):
-    """The hadronic BF16 step at more replicas.  Columns are processed in
-    passes of 128, each streaming the table once."""
+    """The hadronic BF16 step at one replica (the table-streaming bound:
+    HBM GB/s of algorithmic bytes, and from the FETCH/WRITE counters when
+    they were taken on the current source) and at more replicas (passes of
+    128 columns, each streaming the table once)."""
     out = {}
-    for R in (256, 512, 1024):
+    cnt = counters()
+    for R in (1, 256, 512, 1024):
         x = torch.from_numpy(w.pdf(R).astype(np.float32)).cuda()
         y = torch.empty((Ntot, R), dtype=torch.float32, device="cuda")
         fn = lambda: fkconv.fk_conv_had(c.ctx, gb, x, out=y)
@@ -774,6 +777,13 @@ def rsweep(c, w, gb, elems_fwd, Ntot, args, torch, fkconv):
         out[f"R{R}"] = {"ms_per_step": ms, "value": Ntot * R / (ms * 1e-3),
                         "had_fwd_ms_per_step": kms, "passes": (R + 127) // 128,
                         "mfma_tflops": tfl, "mfma_frac": tfl / PEAK_BF16_TFLOPS}
+        if R == 1:
+            byt = elems_fwd * 2 + x.numel() * 4 + Ntot * 4
+            out["R1"]["achieved_gbs"] = byt / (kms * 1e-3) / 1e9
+            r1 = (cnt or {}).get("forward_bf16_R1")
+            if r1:
+                out["R1"]["hbm_bytes_from_counters"] = r1["hbm_bytes_per_launch"]
+                out["R1"]["hbm_gbs_from_counters"] = r1["hbm_bytes_per_launch"] / (kms * 1e-3) / 1e9
     return out
 
 
